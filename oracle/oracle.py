@@ -1,0 +1,181 @@
+"""ctypes wrapper around the scalar CPU oracle (zig_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the reference the GPU library is
+checked against; only the tests, the smoke check and the benchmark's CPU
+baseline may import this module.  It shares no code with the library.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libzig_oracle.so")
+SRC = os.path.join(HERE, "zig_oracle.c")
+
+EXP, NORMAL = 0, 1
+F64, F32 = 0, 1
+MAXI = 1024
+
+
+def build(force=False):
+    """Compile the oracle with gcc: IEEE round-to-nearest, no contraction,
+    no fast-math, so that only the explicit fma calls are fused."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           SRC, "-o", tmp, "-lquadmath", "-lm", "-lpthread"]
+    subprocess.check_call(cmd, cwd=HERE)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class Tables(ctypes.Structure):
+    _fields_ = [
+        ("dist", ctypes.c_int), ("i_max", ctypes.c_uint32), ("b", ctypes.c_uint32), ("L", ctypes.c_uint32),
+        ("X", ctypes.c_double * (MAXI + 1)), ("f", ctypes.c_double * (MAXI + 1)),
+        ("XS", ctypes.c_double * MAXI), ("XS32", ctypes.c_float * MAXI),
+        ("W", ctypes.c_double * (MAXI + 1)), ("H", ctypes.c_double * (MAXI + 1)),
+        ("q", ctypes.c_uint64 * (MAXI + 1)), ("T", ctypes.c_uint64 * MAXI), ("A", ctypes.c_uint32 * MAXI),
+        ("eps", ctypes.c_double), ("K_eps", ctypes.c_uint64), ("X0", ctypes.c_double), ("invX0", ctypes.c_double),
+        ("hpX", (ctypes.c_char * 48) * (MAXI + 1)), ("hpf", (ctypes.c_char * 48) * (MAXI + 1)),
+        ("hpA", (ctypes.c_char * 48) * (MAXI + 1)),
+        ("hp_area", ctypes.c_char * 48), ("hp_total", ctypes.c_char * 48), ("hp_eps", ctypes.c_char * 48),
+    ]
+
+
+_lib = None
+_tables = {}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        u64, u32, i32, dbl, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        tp = ctypes.POINTER(Tables)
+        L.orc_philox4x32_10.argtypes = [ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        L.orc_philox4x32_10.restype = None
+        L.orc_build_tables.argtypes = [i32, u32, tp]
+        L.orc_build_tables.restype = i32
+        L.orc_fill.argtypes = [i32, i32, tp, tp, u64, u64, u64, dbl, dbl, vp, i32]
+        L.orc_fill.restype = i32
+        L.orc_fill_trace.argtypes = [i32, i32, tp, tp, u64, u64, u64, dbl, dbl, vp, vp, vp, vp, vp]
+        L.orc_fill_trace.restype = i32
+        L.orc_box_attempt.argtypes = [tp, u32, u64, u64, ctypes.POINTER(dbl)]
+        L.orc_box_attempt.restype = i32
+        L.orc_box_grid.argtypes = [tp, u32, u32, u32, vp, vp]
+        L.orc_box_grid.restype = i32
+        L.orc_sample_region.argtypes = [tp, tp, i32, u32, u64, u64, u64, vp]
+        L.orc_sample_region.restype = i32
+        L.orc_alias_draw.argtypes = [tp, u64]
+        L.orc_alias_draw.restype = u32
+        L.orc_tables_size.argtypes = []
+        L.orc_tables_size.restype = u64
+        if L.orc_tables_size() != ctypes.sizeof(Tables):
+            raise RuntimeError("oracle table layout mismatch")
+        _lib = L
+    return _lib
+
+
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def tables(dist, i_max=256):
+    key = (dist, i_max)
+    if key not in _tables:
+        t = Tables()
+        if lib().orc_build_tables(dist, i_max, ctypes.byref(t)) != 0:
+            raise ValueError("unsupported table %r" % (key,))
+        _tables[key] = t
+    return _tables[key]
+
+
+def table_arrays(dist, i_max=256):
+    """The tables as numpy arrays (copies)."""
+    t = tables(dist, i_max)
+    L = t.L
+    return {
+        "L": L, "i_max": t.i_max, "b": t.b,
+        "X": np.array(t.X[: L + 1]), "f": np.array(t.f[: L + 1]),
+        "XS": np.array(t.XS[: t.i_max]), "XS32": np.array(t.XS32[: t.i_max], dtype=np.float32),
+        "W": np.array(t.W[: L + 1]), "H": np.array(t.H[: L + 1]),
+        "q": np.array(t.q[: L + 1], dtype=np.uint64),
+        "T": np.array(t.T[: t.i_max], dtype=np.uint64), "A": np.array(t.A[: t.i_max], dtype=np.uint32),
+        "eps": t.eps, "K_eps": int(t.K_eps), "X0": t.X0, "invX0": t.invX0,
+        "hpX": [t.hpX[k].value.decode() for k in range(L + 1)],
+        "hpf": [t.hpf[k].value.decode() for k in range(L + 1)],
+        "hpA": [t.hpA[k].value.decode() for k in range(L + 1)],
+        "hp_area": t.hp_area.decode(), "hp_total": t.hp_total.decode(),
+        "hp_eps": t.hp_eps.decode(),
+    }
+
+
+def _tabs(dist, i_max):
+    ex = tables(EXP, i_max)
+    nt = tables(NORMAL, i_max) if dist == NORMAL else None
+    return ctypes.byref(ex), (ctypes.byref(nt) if nt is not None else None)
+
+
+def fill(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256):
+    out = np.empty(n, dtype=np.float64 if dtype == F64 else np.float32)
+    ex, nt = _tabs(dist, i_max)
+    r = lib().orc_fill(dist, dtype, ex, nt, seed, first, n, scale, shift,
+                       out.ctypes.data if n else None, threads)
+    if r != 0:
+        raise ValueError("orc_fill rejected its arguments")
+    return out
+
+
+def fill_trace(dist, dtype, seed, first, n, scale, shift=0.0, i_max=256):
+    out = np.empty(n, dtype=np.float64 if dtype == F64 else np.float32)
+    layer = np.empty(n, dtype=np.uint32)
+    region = np.empty(n, dtype=np.int32)
+    words = np.empty(n, dtype=np.uint32)
+    tests = np.empty(n, dtype=np.uint32)
+    ex, nt = _tabs(dist, i_max)
+    r = lib().orc_fill_trace(dist, dtype, ex, nt, seed, first, n, scale, shift,
+                             out.ctypes.data, layer.ctypes.data, region.ctypes.data,
+                             words.ctypes.data, tests.ctypes.data)
+    if r != 0:
+        raise ValueError("orc_fill_trace rejected its arguments")
+    return out, layer, region, words, tests
+
+
+def box_attempt(dist, i_max, j, k1, k2):
+    x = ctypes.c_double()
+    r = lib().orc_box_attempt(ctypes.byref(tables(dist, i_max)), j, k1, k2, ctypes.byref(x))
+    if r < 0:
+        raise ValueError("bad box attempt")
+    return bool(r), x.value
+
+
+def box_grid(dist, i_max, j, g, shift):
+    """Attempts of box j over the g x g lattice (a << shift, c << shift)."""
+    acc = np.empty(g * g, dtype=np.uint8)
+    x = np.empty(g * g, dtype=np.float64)
+    r = lib().orc_box_grid(ctypes.byref(tables(dist, i_max)), j, g, shift, acc.ctypes.data, x.ctypes.data)
+    if r != 0:
+        raise ValueError("bad box grid")
+    return acc.reshape(g, g).astype(bool), x.reshape(g, g)
+
+
+def sample_region(dist, j, seed, index0, n, i_max=256):
+    out = np.empty(n, dtype=np.float64)
+    ex, nt = _tabs(dist, i_max)
+    r = lib().orc_sample_region(ex, nt, dist, j, seed, index0, n, out.ctypes.data)
+    if r != 0:
+        raise ValueError("bad region")
+    return out
+
+
+def alias_draw(dist, i_max, r):
+    return int(lib().orc_alias_draw(ctypes.byref(tables(dist, i_max)), r))
