@@ -1,0 +1,165 @@
+"""Benchmark of the gfx950 modified-ziggurat sampler.
+
+One step = the plain fill at its largest single-GPU configuration, FP64:
+2^30 Exp(lambda = 2.5) samples (seed 11) plus 2^30 N(mu = -1, sigma = 3)
+samples (seed 12), each written once to a resident device buffer.  The
+JSON line reports whole-job Gsamples/s, the HBM-write roofline of the fill
+kernel (algorithmic bytes per launch over its average event-timed
+duration), the CPU oracle timed on a bounded sample, and side numbers for
+the other configurations (2^28 normal FP64; the FP32 variants; the batched
+path against per-request launches).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+N_C3 = 1 << 30
+N_C2 = 1 << 28
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def timed_fills(torch, zig, calls, steps, warmup):
+    """Runs `calls` (a list of (fn, bytes)) `steps` times after `warmup`
+    passes; returns (wall seconds, per-launch event durations in ms, bytes
+    per launch)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        for fn, _b in calls:
+            fn()
+    torch.cuda.synchronize()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in calls]
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        for k, (fn, _b) in enumerate(calls):
+            evs[s][k][0].record(stream)
+            fn()
+            evs[s][k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    durs = [[a.elapsed_time(b) for a, b in row] for row in evs]
+    return wall, durs
+
+
+def cpu_baseline(seconds_hint=True):
+    from oracle import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n = 1 << 26  # per distribution, all threads
+    t0 = time.perf_counter()
+    oracle.fill(0, 0, 11, 0, n, 1.0 / 2.5, 0.0, threads=threads)
+    oracle.fill(1, 0, 12, 0, n, 3.0, -1.0, threads=threads)
+    t_all = time.perf_counter() - t0
+    n1 = 1 << 23  # per distribution, one thread
+    t0 = time.perf_counter()
+    oracle.fill(0, 0, 11, 0, n1, 1.0 / 2.5, 0.0, threads=1)
+    oracle.fill(1, 0, 12, 0, n1, 3.0, -1.0, threads=1)
+    t_one = time.perf_counter() - t0
+    return {
+        "value": round(2 * n / t_all / 1e9, 5), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+        "sample": "2^26 Exp(2.5) + 2^26 N(-1,3) FP64 outputs (indices 0..2^26-1 of the benchmark streams), "
+                  "%d threads over contiguous index ranges" % threads,
+        "single_thread": {"value": round(2 * n1 / t_one / 1e9, 5), "unit": "Gsamples/s",
+                          "sample": "2^23 + 2^23 FP64 outputs, 1 thread"},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the sampler shards by index range with no exchange step, "
+              "so only --gpus 1 is run here", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1403_6870_amd import zig
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(0)
+    log("device %s, %d CUs" % (props.name, props.multi_processor_count))
+    zig.zig_build_tables(256)
+
+    out_e = torch.empty(N_C3, dtype=torch.float64, device=dev)
+    out_n = torch.empty(N_C3, dtype=torch.float64, device=dev)
+    out_e.fill_(0.0)
+    out_n.fill_(0.0)
+    calls = [(lambda: zig.fill_exp(out_e, 11, 0, 2.5), N_C3 * 8),
+             (lambda: zig.fill_normal(out_n, 12, 0, -1.0, 3.0), N_C3 * 8)]
+    log("headline: %d steps of 2 x 2^30 FP64 fills" % args.steps)
+    wall, durs = timed_fills(torch, zig, calls, args.steps, args.warmup)
+    samples = 2 * N_C3 * args.steps
+    value = samples / wall / 1e9
+    d = np.array(durs)
+    avg_ms = float(d.mean())
+    bytes_per_launch = N_C3 * 8
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    log("headline: %.2f Gsamples/s, fill kernel %.3f ms avg (exp %.3f, normal %.3f), %.0f GB/s" %
+        (value, avg_ms, d[:, 0].mean(), d[:, 1].mean(), achieved))
+    del out_e, out_n
+    torch.cuda.empty_cache()
+
+    result = {
+        "metric": "Gsamples/s FP64 exp+normal & % HBM-write roofline; batched p50/p99 latency",
+        "value": round(value, 3), "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded Philox4x32-10 streams)",
+        "config": {"workload": "plain fill, FP64: 2^30 Exp(lambda=2.5) seed 11 + 2^30 N(mu=-1, sigma=3) seed 12, "
+                               "256 layers, one launch each, output resident in HBM",
+                   "samples_per_step": 2 * N_C3, "bytes_written_per_step": 2 * N_C3 * 8},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "fill_kernel (FP64, exp and normal launches averaged)",
+                     "per_launch_ms": {"exp": round(float(d[:, 0].mean()), 4),
+                                       "normal": round(float(d[:, 1].mean()), 4)}},
+    }
+
+    if not args.no_extra:
+        extra = {}
+        # 2^28 N(0,1) FP64, single launch
+        out = torch.empty(N_C2, dtype=torch.float64, device=dev)
+        w, dd = timed_fills(torch, zig, [(lambda: zig.fill_normal(out, 7, 0, 0.0, 1.0), N_C2 * 8)], 20, 3)
+        ms = float(np.mean(dd))
+        extra["normal_2^28_f64"] = {"Gsamples/s": round(N_C2 / (ms * 1e-3) / 1e9, 2), "kernel_ms": round(ms, 4),
+                                    "GB/s": round(N_C2 * 8 / (ms * 1e-3) / 1e9, 1)}
+        del out
+        # FP32 variants of the 2^30 fills
+        o32 = torch.empty(N_C3, dtype=torch.float32, device=dev)
+        for name, fn in [("exp_2^30_f32", lambda: zig.fill_exp(o32, 11, 0, 2.5)),
+                         ("normal_2^30_f32", lambda: zig.fill_normal(o32, 12, 0, -1.0, 3.0))]:
+            w, dd = timed_fills(torch, zig, [(fn, N_C3 * 4)], 10, 3)
+            ms = float(np.mean(dd))
+            extra[name] = {"Gsamples/s": round(N_C3 / (ms * 1e-3) / 1e9, 2), "kernel_ms": round(ms, 4),
+                           "GB/s": round(N_C3 * 4 / (ms * 1e-3) / 1e9, 1)}
+        del o32
+        torch.cuda.empty_cache()
+        log("extra: %s" % json.dumps(extra))
+        result["other_configs"] = extra
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline: %s" % json.dumps(result["cpu_baseline"]))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

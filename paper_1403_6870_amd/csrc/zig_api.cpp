@@ -1,0 +1,278 @@
+// C ABI of the sampler library: argument checking, table registry and
+// device upload, launch-shape choice, launches.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "../../include/zig.h"
+#include "zig_internal.hpp"
+#include "zig_tune.hpp"
+
+namespace zig {
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+struct HostPair {
+  HostTable t[2];
+};
+
+std::mutex g_mu;
+std::map<uint32_t, std::unique_ptr<HostPair>> g_host;           // by i_max
+std::map<std::pair<int, uint32_t>, DevTable*> g_dev;               // (device, i_max) -> 2 tables
+
+bool valid_imax(uint32_t i_max) { return i_max >= 8 && i_max <= kMaxLayers && (i_max & (i_max - 1)) == 0; }
+
+// host tables of both distributions; caller holds g_mu
+int host_tables_locked(uint32_t i_max, HostPair** out) {
+  auto it = g_host.find(i_max);
+  if (it != g_host.end()) {
+    *out = it->second.get();
+    return ZIG_OK;
+  }
+  std::unique_ptr<HostPair> hp(new HostPair());
+  for (uint32_t d = 0; d < 2; ++d) {
+    std::string err = build_host_table(d, i_max, &hp->t[d]);
+    if (!err.empty()) return fail(ZIG_ENOTABLES, "table construction: " + err);
+  }
+  *out = hp.get();
+  g_host[i_max] = std::move(hp);
+  return ZIG_OK;
+}
+
+void to_device_layout(const HostTable& h, DevTable* d) {
+  std::memset(d, 0, sizeof(*d));
+  d->dist = h.dist;
+  d->i_max = h.i_max;
+  d->b = h.b;
+  d->L = h.L;
+  d->K_eps = h.K_eps;
+  d->X0 = h.X0;
+  d->invX0 = h.invX0;
+  for (uint32_t i = 0; i < h.i_max; ++i) {
+    d->XS[i] = h.XS[i];
+    d->XS32[i] = h.XS32[i];
+    d->T[i] = h.T[i];
+    d->A[i] = h.A[i];
+  }
+  for (uint32_t j = 0; j <= h.L; ++j) {
+    d->X[j] = h.X[j];
+    d->f[j] = h.f[j];
+    d->W[j] = h.W[j];
+    d->H[j] = h.H[j];
+  }
+}
+
+// device copy for the current device; returns the pair [exp, normal]
+int device_tables(uint32_t i_max, const DevTable** out) {
+  if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, i_max);
+  auto it = g_dev.find(key);
+  if (it != g_dev.end()) {
+    *out = it->second;
+    return ZIG_OK;
+  }
+  HostPair* hp = nullptr;
+  int r = host_tables_locked(i_max, &hp);
+  if (r != ZIG_OK) return r;
+  DevTable host[2];
+  to_device_layout(hp->t[0], &host[0]);
+  to_device_layout(hp->t[1], &host[1]);
+  DevTable* d = nullptr;
+  e = hipMalloc(&d, sizeof(host));
+  if (e != hipSuccess) return fail(ZIG_ENOMEM, std::string("hipMalloc(tables): ") + hipGetErrorString(e));
+  e = hipMemcpy(d, host, sizeof(host), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return fail(ZIG_EHIP, std::string("hipMemcpy(tables): ") + hipGetErrorString(e));
+  }
+  g_dev[key] = d;
+  *out = d;
+  return ZIG_OK;
+}
+
+int check_params(uint32_t dist, double p0, double p1, double* scale, double* shift) {
+  if (dist == kDistExp) {
+    if (!std::isfinite(p0) || !(p0 > 0.0)) return fail(ZIG_EINVAL, "lambda must be finite and > 0");
+    const double s = 1.0 / p0;
+    if (!std::isfinite(s) || !(s > 0.0)) return fail(ZIG_EINVAL, "1/lambda must be finite and > 0");
+    *scale = s;
+    *shift = 0.0;
+    return ZIG_OK;
+  }
+  if (dist == kDistNormal) {
+    if (!std::isfinite(p0)) return fail(ZIG_EINVAL, "mu must be finite");
+    if (!std::isfinite(p1) || !(p1 > 0.0)) return fail(ZIG_EINVAL, "sigma must be finite and > 0");
+    *scale = p1;
+    *shift = p0;
+    return ZIG_OK;
+  }
+  return fail(ZIG_EINVAL, "unknown distribution");
+}
+
+int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0, double p1,
+              void* out, void* stream, const zig_launch* launch, bool trace, uint32_t* t_layer, int32_t* t_region,
+              uint32_t* t_words, uint32_t* t_tests) {
+  g_error.clear();
+  if (dist != kDistExp && dist != kDistNormal) return fail(ZIG_EINVAL, "unknown distribution");
+  if (dtype != kF64 && dtype != kF32) return fail(ZIG_EINVAL, "unknown dtype");
+  double scale = 0.0, shift = 0.0;
+  int r = check_params(dist, p0, p1, &scale, &shift);
+  if (r != ZIG_OK) return r;
+  zig_launch cfg = {0, 0, 0, 0};
+  if (launch) cfg = *launch;
+  const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
+  if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (n == 0) return ZIG_OK;
+  if (out == nullptr) return fail(ZIG_EINVAL, "out is null");
+  const uint64_t esize = dtype == kF64 ? 8 : 4;
+  if (((uintptr_t)out) % esize != 0) return fail(ZIG_EINVAL, "out is not aligned to its element size");
+  if (n - 1 > UINT64_MAX - first) return fail(ZIG_EINVAL, "first_index + n exceeds 2^64");
+
+  Shape sh = tuned_shape(dist, dtype, n);
+  if (cfg.wg) sh.wg = cfg.wg;
+  if (cfg.spl) sh.spl = cfg.spl;
+  if (cfg.queue == ZIG_QUEUE_NONE)
+    sh.queue = 0;
+  else if (cfg.queue)
+    sh.queue = cfg.queue;
+  if (trace) {
+    if (!((sh.wg == 64 && sh.spl == 1) || (sh.wg == 256 && (sh.spl == 2 || sh.spl == 4)))) {
+      sh.wg = 256;
+      sh.spl = 2;
+    }
+  }
+  if (!shape_supported(sh.wg, sh.spl)) return fail(ZIG_EINVAL, "unsupported workgroup size / samples per lane");
+  if (sh.queue > 4096) return fail(ZIG_EINVAL, "queue capacity must be <= 4096");
+
+  const DevTable* tabs = nullptr;
+  r = device_tables(i_max, &tabs);
+  if (r != ZIG_OK) return r;
+
+  const uint64_t per_block = dtype == kF64 ? 2 : 4;
+  const uint64_t last = first + (n - 1);
+  FillArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.seed = seed;
+  a.first = first;
+  a.last = last;
+  a.blk_last = last / per_block;
+  a.out = out;
+  a.scale = scale;
+  a.shift = shift;
+  a.tab = tabs + dist;
+  a.etab = tabs + kDistExp;
+  a.queue = sh.queue;
+  a.aligned16 = ((((uintptr_t)out) - first * esize) & 15u) == 0 ? 1u : 0u;
+  a.t_layer = t_layer;
+  a.t_region = t_region;
+  a.t_words = t_words;
+  a.t_tests = t_tests;
+
+  const uint64_t blk0 = first / per_block;
+  const uint64_t nblk = a.blk_last - blk0 + 1;
+  const uint64_t tile = (uint64_t)sh.wg * sh.spl;
+  const uint64_t tiles = nblk / tile + (nblk % tile != 0);
+  const uint64_t chunk = (1ull << 31) / sh.wg;  // work-items per dispatch stay below 2^31
+  for (uint64_t start = 0; start < tiles; start += chunk) {
+    a.blk0 = blk0 + start * tile;
+    const uint64_t grid = (tiles - start < chunk) ? tiles - start : chunk;
+    int e = launch_fill(dist, dtype, sh.wg, sh.spl, trace, grid, a, stream);
+    if (e != 0)
+      return fail(ZIG_EHIP, std::string("fill launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
+  }
+  return ZIG_OK;
+}
+
+}  // namespace
+
+int device_tables_for(uint32_t i_max, const DevTable** out) { return device_tables(i_max, out); }
+int params_for(uint32_t dist, double p0, double p1, double* scale, double* shift) {
+  return check_params(dist, p0, p1, scale, shift);
+}
+void set_error(const std::string& msg) { g_error = msg; }
+
+}  // namespace zig
+
+extern "C" {
+
+int zig_build_tables(uint32_t i_max) {
+  zig::g_error.clear();
+  const zig::DevTable* t = nullptr;
+  return zig::device_tables(i_max, &t);
+}
+
+int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out) {
+  zig::g_error.clear();
+  if (out == nullptr) return zig::fail(ZIG_EINVAL, "out is null");
+  if (dist > 1) return zig::fail(ZIG_EINVAL, "unknown distribution");
+  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  std::lock_guard<std::mutex> lk(zig::g_mu);
+  zig::HostPair* hp = nullptr;
+  int r = zig::host_tables_locked(i_max, &hp);
+  if (r != ZIG_OK) return r;
+  const zig::HostTable& t = hp->t[dist];
+  out->dist = t.dist;
+  out->i_max = t.i_max;
+  out->b = t.b;
+  out->L = t.L;
+  out->X = t.X.data();
+  out->f = t.f.data();
+  out->XS = t.XS.data();
+  out->XS32 = t.XS32.data();
+  out->W = t.W.data();
+  out->H = t.H.data();
+  out->q = t.q.data();
+  out->T = t.T.data();
+  out->alias = t.A.data();
+  out->eps = t.eps;
+  out->K_eps = t.K_eps;
+  out->X0 = t.X0;
+  out->invX0 = t.invX0;
+  return ZIG_OK;
+}
+
+int zig_fill(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
+             void* out, void* stream, const zig_launch* launch) {
+  return zig::fill_impl(dist, dtype, seed, first_index, n, p0, p1, out, stream, launch, false, nullptr, nullptr,
+                        nullptr, nullptr);
+}
+
+int zig_fill_exp(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dtype, double lambda, void* out,
+                 void* stream) {
+  return zig::fill_impl(ZIG_EXP, dtype, seed, first_index, n, lambda, 0.0, out, stream, nullptr, false, nullptr,
+                        nullptr, nullptr, nullptr);
+}
+
+int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dtype, double mu, double sigma,
+                    void* out, void* stream) {
+  return zig::fill_impl(ZIG_NORMAL, dtype, seed, first_index, n, mu, sigma, out, stream, nullptr, false, nullptr,
+                        nullptr, nullptr, nullptr);
+}
+
+int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0,
+                   double p1, void* out, uint32_t* layer, int32_t* region, uint32_t* words, uint32_t* tests,
+                   void* stream, const zig_launch* launch) {
+  return zig::fill_impl(dist, dtype, seed, first_index, n, p0, p1, out, stream, launch, true, layer, region, words,
+                        tests);
+}
+
+const char* zig_last_error(void) { return zig::g_error.c_str(); }
+
+const char* zig_version(void) { return "zigrand 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Device-side pieces of the modified ziggurat sampler for gfx950: the
+// Philox4x32-10 uniform source, the per-output slow stream, the alias draw
+// and the rejection/tail paths.  The fast path lives in the kernels, which
+// keep its table in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "zig_internal.hpp"
+
+namespace zig {
+namespace dev {
+
+constexpr uint64_t kOne53 = 1ull << 53;
+
+// Philox4x32-10 (Salmon et al., SC'11): per round two 32x32->64 products,
+// the high halves folded into the other pair of words with the round key;
+// the key is bumped by the Weyl constants between rounds.  The key is the
+// same for every lane, so its schedule stays in scalar registers.
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                         uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t a = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t b = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = a;
+    c2 = b;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Word t of the slow stream of output g comes from the block with counter
+// (g lo, g hi, t >> 1, 2): words 0|1 for even t, 2|3 for odd t.  One block
+// serves two consecutive words.
+struct SlowStream {
+  uint32_t g0, g1, k0, k1;
+  uint32_t t;
+  uint32_t spare_lo, spare_hi;
+
+  __device__ __forceinline__ SlowStream(uint64_t g, uint32_t key0, uint32_t key1)
+      : g0((uint32_t)g), g1((uint32_t)(g >> 32)), k0(key0), k1(key1), t(0), spare_lo(0), spare_hi(0) {}
+
+  __device__ __forceinline__ uint64_t next() {
+    uint64_t w;
+    if ((t & 1u) == 0) {
+      uint32_t c0 = g0, c1 = g1, c2 = t >> 1, c3 = 2u;
+      philox10(c0, c1, c2, c3, k0, k1);
+      w = (uint64_t)c0 | ((uint64_t)c1 << 32);
+      spare_lo = c2;
+      spare_hi = c3;
+    } else {
+      w = (uint64_t)spare_lo | ((uint64_t)spare_hi << 32);
+    }
+    ++t;
+    return w;
+  }
+};
+
+// Region draw: column c from the low b bits, compare the high 64-b bits
+// with the column threshold, else take the column's alias.
+__device__ __forceinline__ uint32_t alias_region(const DevTable* tb, uint64_t r) {
+  const uint32_t c = (uint32_t)r & (tb->i_max - 1);
+  return (r >> tb->b) < tb->T[c] ? c : tb->A[c];
+}
+
+__device__ __forceinline__ double lattice53(uint64_t k) { return (double)k * 0x1p-53; }
+
+// Exponential draw after its fast word failed (layer index >= L): region j
+// from the alias table; the tail (j = 0) is X_0 plus a fresh exponential,
+// whose own fast word is the next slow word (tail nesting adds X_0 once per
+// level, innermost first); a box is sampled by reflection across the chord,
+// the eps band shortcut and the exact test, retrying in the same box.
+// `first_region` receives the first j drawn, `tests` counts exp() calls.
+__device__ __noinline__ double exp_slow(const DevTable* E, SlowStream& s, int32_t& first_region, uint32_t& tests) {
+  uint32_t nest = 0;
+  double y = 0.0;
+  bool first = true;
+  for (;;) {
+    const uint32_t j = alias_region(E, s.next());
+    if (first) {
+      first_region = (int32_t)j;
+      first = false;
+    }
+    if (j == 0) {
+      ++nest;
+      const uint64_t w = s.next();
+      const uint32_t i = (uint32_t)w & (E->i_max - 1);
+      if (i < E->L) {
+        y = (double)(w >> 11) * E->XS[i];
+        break;
+      }
+      continue;
+    }
+    const double left = E->X[j], width = E->W[j], height = E->H[j], base = E->f[j - 1];
+    const uint64_t keps = E->K_eps;
+    for (;;) {
+      uint64_t k1 = s.next() >> 11;
+      uint64_t k2 = s.next() >> 11;
+      if (k1 + k2 > kOne53) {
+        const uint64_t r1 = kOne53 - k2;
+        k2 = kOne53 - k1;
+        k1 = r1;
+      }
+      const double x = __builtin_fma(lattice53(k1), width, left);
+      if (k1 + k2 <= keps) {
+        y = x;
+        break;
+      }
+      const double yy = __builtin_fma(lattice53(k2), height, base);
+      ++tests;
+      if (yy < exp(-x)) {
+        y = x;
+        break;
+      }
+    }
+    break;
+  }
+  for (uint32_t c = 0; c < nest; ++c) y = E->X0 + y;
+  return y;
+}
+
+// The whole exponential sampler started from fast word w.
+__device__ __forceinline__ double exp_from_word(const DevTable* E, uint64_t w, SlowStream& s, uint32_t& tests) {
+  const uint32_t i = (uint32_t)w & (E->i_max - 1);
+  if (i < E->L) return (double)(w >> 11) * E->XS[i];
+  int32_t unused;
+  return exp_slow(E, s, unused, tests);
+}
+
+// Normal magnitude after its fast word failed: region j; the tail uses
+// Marsaglia's method with two exponential draws E1, E2 (t = E1 / X_0,
+// accept when 2 E2 > t^2, return X_0 + t); a box is sampled by plain
+// rejection against e^{-x^2/2}, retrying in the same box.
+__device__ __noinline__ double normal_slow(const DevTable* N, const DevTable* E, SlowStream& s, int32_t& first_region,
+                                           uint32_t& tests) {
+  const uint32_t j = alias_region(N, s.next());
+  first_region = (int32_t)j;
+  if (j == 0) {
+    for (;;) {
+      const double e1 = exp_from_word(E, s.next(), s, tests);
+      const double e2 = exp_from_word(E, s.next(), s, tests);
+      const double t = e1 * N->invX0;
+      if (e2 + e2 > t * t) return N->X0 + t;
+    }
+  }
+  const double left = N->X[j], width = N->W[j], height = N->H[j], base = N->f[j - 1];
+  for (;;) {
+    const uint64_t k1 = s.next() >> 11;
+    const uint64_t k2 = s.next() >> 11;
+    const double x = __builtin_fma(lattice53(k1), width, left);
+    const double yy = __builtin_fma(lattice53(k2), height, base);
+    ++tests;
+    if (yy < exp(-0.5 * (x * x))) return x;
+  }
+}
+
+// Magnitude of output g on its slow path.
+template <uint32_t DIST>
+__device__ __forceinline__ double slow_magnitude(const DevTable* tab, const DevTable* etab, uint64_t g, uint32_t k0,
+                                                 uint32_t k1, int32_t& region, uint32_t& words, uint32_t& tests) {
+  SlowStream s(g, k0, k1);
+  tests = 0;
+  double m;
+  if constexpr (DIST == kDistExp)
+    m = exp_slow(tab, s, region, tests);
+  else
+    m = normal_slow(tab, etab, s, region, tests);
+  words = s.t;
+  return m;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+}  // namespace dev
+}  // namespace zig

@@ -1,0 +1,76 @@
+// Internal declarations shared by the library's host and device sources.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace zig {
+
+constexpr uint32_t kMaxLayers = 256;  // largest supported i_max
+constexpr uint32_t kDistExp = 0;
+constexpr uint32_t kDistNormal = 1;
+constexpr uint32_t kF64 = 0;
+constexpr uint32_t kF32 = 1;
+
+// Tables of one distribution as the kernels read them (device memory).
+// Layers i < L; X[L] = 0 and f[L] = 1 close the cap; box j (1..L) spans
+// [X[j], X[j] + W[j]] x [f[j-1], f[j-1] + H[j]].
+struct DevTable {
+  uint32_t dist, i_max, b, L;
+  uint64_t K_eps;
+  double X0, invX0;
+  double XS[kMaxLayers];
+  float XS32[kMaxLayers];
+  double X[kMaxLayers + 1];
+  double f[kMaxLayers + 1];
+  double W[kMaxLayers + 1];
+  double H[kMaxLayers + 1];
+  uint64_t T[kMaxLayers];
+  uint32_t A[kMaxLayers];
+};
+
+// g++ builds the host side and hipcc the device side: both must agree
+static_assert(sizeof(DevTable) == 14408, "DevTable layout");
+
+// Host copy with the same content plus the quantities only tests need.
+struct HostTable {
+  uint32_t dist = 0, i_max = 0, b = 0, L = 0;
+  std::vector<double> X, f, XS, W, H;
+  std::vector<float> XS32;
+  std::vector<uint64_t> q, T;
+  std::vector<uint32_t> A;
+  double eps = 0.0, X0 = 0.0, invX0 = 0.0;
+  uint64_t K_eps = 0;
+};
+
+// Builds one distribution's tables in binary128 (zig_tables.cpp).
+// Returns an empty string on success, else a message.
+std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out);
+
+// Kernel-side argument block of a plain fill.
+struct FillArgs {
+  uint64_t seed;
+  uint64_t first;     // first global output index
+  uint64_t last;      // last global output index (inclusive)
+  uint64_t blk0;      // first Philox block of this launch
+  uint64_t blk_last;  // last Philox block of the whole fill
+  void* out;          // element 0 of the caller's buffer (index `first`)
+  double scale, shift;
+  const DevTable* tab;   // tables of the distribution
+  const DevTable* etab;  // exponential tables (normal tail)
+  uint32_t queue;        // LDS queue capacity
+  uint32_t aligned16;    // 16-byte block stores are aligned
+  // trace arrays (trace build only), indexed by output - first
+  uint32_t* t_layer;
+  int32_t* t_region;
+  uint32_t* t_words;
+  uint32_t* t_tests;
+};
+
+// Launch of one (dist, dtype, wg, spl) variant; defined in zig_fill.hip.
+// Returns 0 or a hipError_t value.
+int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, uint64_t grid,
+                const FillArgs& a, void* stream);
+
+}  // namespace zig

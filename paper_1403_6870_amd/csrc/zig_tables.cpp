@@ -1,0 +1,232 @@
+// Host construction of the ziggurat tables in binary128 (__float128).
+//
+// Section 2 of McFarland's paper: layers of equal area 1/i_max of the total
+// lie under the density, each with its upper-right corner (X_i, P(X_i)) on
+// the curve and its lower-left corner at (0, P(X_{i-1})), so that
+//   X_i (P(X_i) - P(X_{i-1})) = area,
+// solved bottom up until no further layer fits.  The rest of the mass lies
+// in the tail beyond X_0, in the overhang right of each layer and in the cap
+// above the top layer; the sampler picks one of those regions with
+// probability proportional to its area.  Appendix B: the tables are computed
+// in 128-bit precision and rounded once to double.
+//
+// Each layer's length is found by a bracketed Newton iteration on the layer
+// equation (bisection whenever a Newton step leaves the bracket), starting
+// from the maximiser of X (P(X) - P(X_{i-1})), itself found the same way.
+#include <quadmath.h>
+
+#include <cmath>
+#include <deque>
+
+#include "zig_internal.hpp"
+
+namespace zig {
+namespace {
+
+using q128 = __float128;
+
+struct Density {
+  uint32_t dist;
+  q128 p(q128 x) const { return dist == kDistExp ? expq(-x) : expq(-0.5Q * x * x); }
+  q128 dp(q128 x) const { return dist == kDistExp ? -expq(-x) : -x * expq(-0.5Q * x * x); }
+  q128 d2p(q128 x) const { return dist == kDistExp ? expq(-x) : (x * x - 1) * expq(-0.5Q * x * x); }
+  q128 total() const { return dist == kDistExp ? (q128)1 : sqrtq(M_PIq * 0.5Q); }
+  // integral of p over [x, infinity)
+  q128 upper(q128 x) const {
+    if (dist == kDistExp) return expq(-x);
+    return sqrtq(M_PIq * 0.5Q) * erfcq(x * M_SQRT1_2q);
+  }
+  // integral of p over [lo, hi]
+  q128 between(q128 lo, q128 hi) const {
+    if (dist == kDistExp) return expq(-lo) * -expm1q(lo - hi);
+    if (lo >= 1) return upper(lo) - upper(hi);
+    return sqrtq(M_PIq * 0.5Q) * (erfq(hi * M_SQRT1_2q) - erfq(lo * M_SQRT1_2q));
+  }
+};
+
+// Root of fn in [lo, hi] (fn changes sign there) by Newton steps kept inside
+// a shrinking bracket.
+template <class F, class DF>
+q128 bracketed_newton(F fn, DF dfn, q128 lo, q128 hi) {
+  q128 flo = fn(lo);
+  q128 xneg = lo, xpos = hi;  // fn(xneg) < 0 <= fn(xpos)
+  if (flo >= 0) {
+    xneg = hi;
+    xpos = lo;
+  }
+  q128 x = 0.5Q * (lo + hi);
+  q128 step_old = fabsq(hi - lo), step = step_old;
+  q128 fx = fn(x), dfx = dfn(x);
+  if (fx < 0)
+    xneg = x;
+  else
+    xpos = x;
+  for (int it = 0; it < 600; ++it) {
+    const bool outside = ((x - xpos) * dfx - fx) * ((x - xneg) * dfx - fx) > 0;
+    const bool slow = fabsq(2 * fx) > fabsq(step_old * dfx);
+    q128 prev = x;
+    if (outside || slow || dfx == 0) {
+      step_old = step;
+      step = 0.5Q * (xpos - xneg);
+      x = xneg + step;
+    } else {
+      step_old = step;
+      step = fx / dfx;
+      x = x - step;
+    }
+    if (x == prev) break;  // the bracket cannot shrink any further
+    if (fabsq(x - prev) <= fabsq(x) * 0x1p-112Q) break;  // Newton converged
+    fx = fn(x);
+    dfx = dfn(x);
+    if (fx < 0)
+      xneg = x;
+    else
+      xpos = x;
+  }
+  return x;
+}
+
+// round-half-even of a non-negative binary128 value below 2^64
+uint64_t round_half_even(q128 v) {
+  q128 fl = floorq(v);
+  q128 frac = v - fl;
+  uint64_t r = (uint64_t)fl;
+  if (frac > 0.5Q || (frac == 0.5Q && (r & 1))) r += 1;
+  return r;
+}
+
+}  // namespace
+
+std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out) {
+  if (dist != kDistExp && dist != kDistNormal) return "unknown distribution";
+  uint32_t b = 0;
+  while (b < 31 && (1u << b) < i_max) ++b;
+  if ((1u << b) != i_max || i_max < 8 || i_max > kMaxLayers) return "i_max must be a power of two in [8, 256]";
+
+  const Density P{dist};
+  const q128 area = P.total() / i_max;
+  std::vector<q128> Xq, fq;
+  q128 f_below = 0;
+  q128 X_below = 64;  // P is negligible there for both densities
+  while (Xq.size() < i_max) {
+    auto g = [&](q128 x) { return x * (P.p(x) - f_below); };
+    auto dg = [&](q128 x) { return P.p(x) - f_below + x * P.dp(x); };
+    auto d2g = [&](q128 x) { return 2 * P.dp(x) + x * P.d2p(x); };
+    const q128 x_peak = bracketed_newton(dg, d2g, (q128)0, X_below);
+    if (g(x_peak) < area) break;
+    auto h = [&](q128 x) { return g(x) - area; };
+    const q128 x_new = bracketed_newton(h, dg, x_peak, X_below);
+    Xq.push_back(x_new);
+    fq.push_back(P.p(x_new));
+    f_below = fq.back();
+    X_below = x_new;
+  }
+  const uint32_t L = (uint32_t)Xq.size();
+  if (L < 1 || L >= i_max) return "layer construction failed";
+
+  HostTable& t = *out;
+  t = HostTable();
+  t.dist = dist;
+  t.i_max = i_max;
+  t.b = b;
+  t.L = L;
+  t.X.assign(L + 1, 0.0);
+  t.f.assign(L + 1, 1.0);
+  for (uint32_t i = 0; i < L; ++i) {
+    t.X[i] = (double)Xq[i];
+    t.f[i] = (double)fq[i];
+  }
+  t.XS.assign(i_max, 0.0);
+  t.XS32.assign(i_max, 0.0f);
+  const int e32 = dist == kDistExp ? -24 : -23;
+  for (uint32_t i = 0; i < L; ++i) {
+    t.XS[i] = std::ldexp(t.X[i], -53);
+    t.XS32[i] = std::ldexp((float)Xq[i], e32);
+  }
+  t.W.assign(L + 1, 0.0);
+  t.H.assign(L + 1, 0.0);
+  for (uint32_t j = 1; j <= L; ++j) {
+    t.W[j] = t.X[j - 1] - t.X[j];
+    t.H[j] = t.f[j] - t.f[j - 1];
+  }
+
+  // region masses: tail, overhang right of each layer, cap
+  std::vector<q128> mass(L + 1);
+  mass[0] = P.upper(Xq[0]);
+  for (uint32_t j = 1; j <= L; ++j) {
+    const q128 right = Xq[j - 1];
+    const q128 left = (j == L) ? (q128)0 : Xq[j];
+    mass[j] = P.between(left, right) - fq[j - 1] * (right - left);
+  }
+  q128 msum = 0;
+  for (q128 m : mass) msum += m;
+  t.q.assign(L + 1, 0);
+  unsigned __int128 used = 0;
+  const q128 two64 = 18446744073709551616.0Q;
+  for (uint32_t j = 0; j < L; ++j) {
+    t.q[j] = round_half_even(mass[j] / msum * two64);
+    used += t.q[j];
+  }
+  const unsigned __int128 total_weight = (unsigned __int128)1 << 64;
+  if (used >= total_weight) return "region weights overflow";
+  t.q[L] = (uint64_t)(total_weight - used);
+
+  // alias table (Vose) in exact integers; small and large columns are
+  // served first-in first-out in ascending column order
+  const uint64_t cap = (uint64_t)1 << (64 - b);
+  t.T.assign(i_max, 0);
+  t.A.assign(i_max, 0);
+  std::vector<uint64_t> rest(i_max, 0);
+  for (uint32_t c = 0; c <= L; ++c) rest[c] = t.q[c];
+  std::deque<uint32_t> small, large;
+  for (uint32_t c = 0; c < i_max; ++c) {
+    if (rest[c] < cap) {
+      small.push_back(c);
+    } else if (rest[c] > cap) {
+      large.push_back(c);
+    } else {
+      t.T[c] = cap;
+      t.A[c] = c;
+    }
+  }
+  while (!small.empty()) {
+    if (large.empty()) return "alias construction failed";
+    const uint32_t s = small.front();
+    small.pop_front();
+    const uint32_t g = large.front();
+    t.T[s] = rest[s];
+    t.A[s] = g;
+    rest[g] -= cap - rest[s];
+    if (rest[g] <= cap) {
+      large.pop_front();
+      if (rest[g] < cap) {
+        small.push_back(g);
+      } else {
+        t.T[g] = cap;
+        t.A[g] = g;
+      }
+    }
+  }
+  if (!large.empty()) return "alias construction left weight";
+
+  // exponential boxes: largest normalised gap between chord and curve;
+  // in a box of width w the curve is (e^{-wu} - e^{-w}) / (1 - e^{-w})
+  if (dist == kDistExp) {
+    q128 eps = 0;
+    for (uint32_t j = 1; j <= L; ++j) {
+      const q128 w = Xq[j - 1] - ((j == L) ? (q128)0 : Xq[j]);
+      const q128 one_minus = -expm1q(-w);  // 1 - e^{-w}
+      const q128 slope = one_minus / w;    // e^{-w u*} where the gap peaks
+      const q128 u_star = -logq(slope) / w;
+      const q128 gap = 1 - u_star - (slope - expq(-w)) / one_minus;
+      if (gap > eps) eps = gap;
+    }
+    t.eps = (double)eps;
+    t.K_eps = (uint64_t)floorq((1 - eps) * 9007199254740992.0Q);
+  }
+  t.X0 = t.X[0];
+  t.invX0 = (double)(1 / Xq[0]);
+  return std::string();
+}
+
+}  // namespace zig

@@ -1,0 +1,185 @@
+"""Python binding of libzig.so, the gfx950 modified-ziggurat sampler.
+
+Argument marshalling only: every sample is produced by the library's HIP
+kernels.  The functions named zig_* mirror the C ABI in include/zig.h one
+to one (pointers are plain integers); fill_exp / fill_normal / fill /
+fill_batch are conveniences that take torch tensors for device memory and
+torch streams.  If the library has not been built, importing this module
+raises ImportError: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzig.so")
+
+ZIG_OK, ZIG_EINVAL, ZIG_ENOTABLES, ZIG_EHIP, ZIG_ENOMEM, ZIG_EBUSY, ZIG_ESTATE = range(7)
+EXP, NORMAL = 0, 1
+QUEUE_NONE = 0xFFFFFFFF
+F64, F32 = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libzig.so is not built (run __graft_entry__.build() or paper_1403_6870_amd/build_lib.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+u32, u64, i32, dbl, vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+
+
+class ZigError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("zig status %d: %s" % (status, msg))
+        self.status = status
+
+
+class TableView(ctypes.Structure):
+    _fields_ = [("dist", u32), ("i_max", u32), ("b", u32), ("L", u32),
+                ("X", ctypes.POINTER(dbl)), ("f", ctypes.POINTER(dbl)), ("XS", ctypes.POINTER(dbl)),
+                ("XS32", ctypes.POINTER(ctypes.c_float)), ("W", ctypes.POINTER(dbl)), ("H", ctypes.POINTER(dbl)),
+                ("q", ctypes.POINTER(u64)), ("T", ctypes.POINTER(u64)), ("alias", ctypes.POINTER(u32)),
+                ("eps", dbl), ("K_eps", u64), ("X0", dbl), ("invX0", dbl)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("i_max", u32), ("wg", u32), ("spl", u32), ("queue", u32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_build = _sig("zig_build_tables", i32, [u32])
+_get = _sig("zig_get_tables", i32, [u32, u32, ctypes.POINTER(TableView)])
+_fill_exp = _sig("zig_fill_exp", i32, [u64, u64, u64, u32, dbl, vp, vp])
+_fill_normal = _sig("zig_fill_normal", i32, [u64, u64, u64, u32, dbl, dbl, vp, vp])
+_fill = _sig("zig_fill", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, ctypes.POINTER(Launch)])
+_fill_trace = _sig("zig_fill_trace", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, vp, vp, vp, vp,
+                                           ctypes.POINTER(Launch)])
+_last_error = _sig("zig_last_error", ctypes.c_char_p, [])
+_version = _sig("zig_version", ctypes.c_char_p, [])
+
+EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
+           "zig_last_error", "zig_version"]
+
+
+def zig_last_error():
+    return _last_error().decode()
+
+
+def zig_version():
+    return _version().decode()
+
+
+def _check(status):
+    if status != ZIG_OK:
+        raise ZigError(status, zig_last_error())
+
+
+def _launch(launch):
+    if launch is None:
+        return None
+    if isinstance(launch, Launch):
+        return ctypes.byref(launch)
+    return ctypes.byref(Launch(launch.get("i_max", 0), launch.get("wg", 0), launch.get("spl", 0),
+                               launch.get("queue", 0)))
+
+
+def zig_build_tables(i_max=256):
+    _check(_build(i_max))
+
+
+def zig_get_tables(dist, i_max=256):
+    v = TableView()
+    _check(_get(dist, i_max, ctypes.byref(v)))
+    L, im = v.L, v.i_max
+    arr = lambda p, k, dt: np.ctypeslib.as_array(p, shape=(k,)).astype(dt).copy()
+    return {
+        "dist": v.dist, "i_max": im, "b": v.b, "L": L,
+        "X": arr(v.X, L + 1, np.float64), "f": arr(v.f, L + 1, np.float64),
+        "XS": arr(v.XS, im, np.float64), "XS32": arr(v.XS32, im, np.float32),
+        "W": arr(v.W, L + 1, np.float64), "H": arr(v.H, L + 1, np.float64),
+        "q": arr(v.q, L + 1, np.uint64), "T": arr(v.T, im, np.uint64), "A": arr(v.alias, im, np.uint32),
+        "eps": v.eps, "K_eps": int(v.K_eps), "X0": v.X0, "invX0": v.invX0,
+    }
+
+
+def zig_fill_exp(seed, first_index, n, dtype, lam, out_ptr, stream_ptr=None):
+    _check(_fill_exp(seed, first_index, n, dtype, lam, out_ptr, stream_ptr))
+
+
+def zig_fill_normal(seed, first_index, n, dtype, mu, sigma, out_ptr, stream_ptr=None):
+    _check(_fill_normal(seed, first_index, n, dtype, mu, sigma, out_ptr, stream_ptr))
+
+
+def zig_fill(dist, dtype, seed, first_index, n, p0, p1, out_ptr, stream_ptr=None, launch=None):
+    _check(_fill(dist, dtype, seed, first_index, n, p0, p1, out_ptr, stream_ptr, _launch(launch)))
+
+
+def zig_fill_trace(dist, dtype, seed, first_index, n, p0, p1, out_ptr, layer_ptr, region_ptr, words_ptr, tests_ptr,
+                   stream_ptr=None, launch=None):
+    _check(_fill_trace(dist, dtype, seed, first_index, n, p0, p1, out_ptr, layer_ptr, region_ptr, words_ptr,
+                       tests_ptr, stream_ptr, _launch(launch)))
+
+
+# ---- torch conveniences -------------------------------------------------
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("output tensor must be float64 or float32")
+
+
+def _check_out(out):
+    if not out.is_cuda or not out.is_contiguous():
+        raise ValueError("output must be a contiguous device tensor")
+
+
+def fill(out, dist, seed, first_index=0, p0=1.0, p1=1.0, launch=None, stream=None):
+    """Fill a contiguous float64/float32 device tensor with samples
+    first_index .. first_index + numel - 1; dist EXP (p0 = lambda) or
+    NORMAL (p0 = mu, p1 = sigma)."""
+    _check_out(out)
+    zig_fill(dist, _dtype_code(out), seed, first_index, out.numel(), p0, p1, out.data_ptr(), _stream_ptr(stream),
+             launch)
+    return out
+
+
+def fill_exp(out, seed, first_index=0, lam=1.0, stream=None):
+    _check_out(out)
+    zig_fill_exp(seed, first_index, out.numel(), _dtype_code(out), lam, out.data_ptr(), _stream_ptr(stream))
+    return out
+
+
+def fill_normal(out, seed, first_index=0, mu=0.0, sigma=1.0, stream=None):
+    _check_out(out)
+    zig_fill_normal(seed, first_index, out.numel(), _dtype_code(out), mu, sigma, out.data_ptr(), _stream_ptr(stream))
+    return out
+
+
+def fill_trace(out, dist, seed, first_index=0, p0=1.0, p1=1.0, launch=None, stream=None):
+    """Debug fill that also returns per-output (layer, region, words,
+    tests) device tensors."""
+    import torch
+    _check_out(out)
+    n = out.numel()
+    layer = torch.empty(n, dtype=torch.int32, device=out.device)
+    region = torch.empty(n, dtype=torch.int32, device=out.device)
+    words = torch.empty(n, dtype=torch.int32, device=out.device)
+    tests = torch.empty(n, dtype=torch.int32, device=out.device)
+    zig_fill_trace(dist, _dtype_code(out), seed, first_index, n, p0, p1, out.data_ptr(), layer.data_ptr(),
+                   region.data_ptr(), words.data_ptr(), tests.data_ptr(), _stream_ptr(stream), launch)
+    return out, layer, region, words, tests
