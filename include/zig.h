@@ -117,17 +117,14 @@ int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dt
                     void* out, void* stream);
 
 /* Launch shape and table size for zig_fill.  Zero fields mean "pick":
- * i_max 256; wg/spl/queue from the tuned table.  wg in {64,128,256,512}
- * lanes per workgroup, spl in {1,2,4,8} Philox blocks per lane per tile,
- * queue = slow-lane queue capacity per workgroup (entries, <= 4096;
- * lanes beyond it finish their slow work in place; ZIG_QUEUE_NONE sends
- * every slow output down the in-place path). */
-#define ZIG_QUEUE_NONE 0xFFFFFFFFu
+ * i_max 256; wg/spl from the tuned table.  wg in {64,128,256,512} lanes
+ * per workgroup and spl in {1,2,4,8} Philox blocks per lane make a tile
+ * of wg * spl blocks (at most 2048), which is also the depth of the
+ * per-workgroup slow-output queue. */
 typedef struct {
   uint32_t i_max;
   uint32_t wg;
   uint32_t spl;
-  uint32_t queue;
 } zig_launch;
 
 /* Generic fill: dist ZIG_EXP (p0 = lambda, p1 ignored) or ZIG_NORMAL

@@ -105,6 +105,33 @@ int device_tables(uint32_t i_max, const DevTable** out) {
   return ZIG_OK;
 }
 
+// Tile counters of the persistent fill kernel, one pair per (device,
+// stream): launches on one stream run in order and each leaves its pair at
+// zero, so a stream can reuse its pair without any reset work.
+std::mutex g_cmu;
+std::map<std::pair<int, void*>, uint32_t*> g_counters;
+
+int stream_counters(void* stream, uint32_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_cmu);
+  auto key = std::make_pair(dev, stream);
+  auto it = g_counters.find(key);
+  if (it != g_counters.end()) {
+    *out = it->second;
+    return ZIG_OK;
+  }
+  uint32_t* c = nullptr;
+  e = hipMalloc(&c, 2 * sizeof(uint32_t));
+  if (e != hipSuccess) return fail(ZIG_ENOMEM, std::string("hipMalloc(counters): ") + hipGetErrorString(e));
+  e = hipMemset(c, 0, 2 * sizeof(uint32_t));
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipMemset(counters): ") + hipGetErrorString(e));
+  g_counters[key] = c;
+  *out = c;
+  return ZIG_OK;
+}
+
 int check_params(uint32_t dist, double p0, double p1, double* scale, double* shift) {
   if (dist == kDistExp) {
     if (!std::isfinite(p0) || !(p0 > 0.0)) return fail(ZIG_EINVAL, "lambda must be finite and > 0");
@@ -133,7 +160,7 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   double scale = 0.0, shift = 0.0;
   int r = check_params(dist, p0, p1, &scale, &shift);
   if (r != ZIG_OK) return r;
-  zig_launch cfg = {0, 0, 0, 0};
+  zig_launch cfg = {0, 0, 0};
   if (launch) cfg = *launch;
   const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
   if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
@@ -146,10 +173,7 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   Shape sh = tuned_shape(dist, dtype, n);
   if (cfg.wg) sh.wg = cfg.wg;
   if (cfg.spl) sh.spl = cfg.spl;
-  if (cfg.queue == ZIG_QUEUE_NONE)
-    sh.queue = 0;
-  else if (cfg.queue)
-    sh.queue = cfg.queue;
+  if (cfg.wg || cfg.spl) sh.chunk = 16384 / (sh.wg * sh.spl) ? 16384 / (sh.wg * sh.spl) : 1;
   if (trace) {
     if (!((sh.wg == 64 && sh.spl == 1) || (sh.wg == 256 && (sh.spl == 2 || sh.spl == 4)))) {
       sh.wg = 256;
@@ -157,7 +181,6 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
     }
   }
   if (!shape_supported(sh.wg, sh.spl)) return fail(ZIG_EINVAL, "unsupported workgroup size / samples per lane");
-  if (sh.queue > 4096) return fail(ZIG_EINVAL, "queue capacity must be <= 4096");
 
   const DevTable* tabs = nullptr;
   r = device_tables(i_max, &tabs);
@@ -176,22 +199,34 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   a.shift = shift;
   a.tab = tabs + dist;
   a.etab = tabs + kDistExp;
-  a.queue = sh.queue;
   a.aligned16 = ((((uintptr_t)out) - first * esize) & 15u) == 0 ? 1u : 0u;
   a.t_layer = t_layer;
   a.t_region = t_region;
   a.t_words = t_words;
   a.t_tests = t_tests;
 
+  r = stream_counters(stream, &a.counters);
+  if (r != ZIG_OK) return r;
+  // blocks whose outputs all lie in [first, last]
+  a.full_lo = first / per_block + (first % per_block != 0);
+  if (last % per_block == per_block - 1) {
+    a.full_hi = last / per_block;
+    a.has_full = a.full_lo <= a.full_hi;
+  } else {
+    a.full_hi = last / per_block == 0 ? 0 : last / per_block - 1;
+    a.has_full = last / per_block > 0 && a.full_lo <= a.full_hi;
+  }
+
   const uint64_t blk0 = first / per_block;
   const uint64_t nblk = a.blk_last - blk0 + 1;
   const uint64_t tile = (uint64_t)sh.wg * sh.spl;
   const uint64_t tiles = nblk / tile + (nblk % tile != 0);
-  const uint64_t chunk = (1ull << 31) / sh.wg;  // work-items per dispatch stay below 2^31
+  const uint64_t chunk = 1ull << 30;  // tiles per launch: the counter stays far from 2^32
   for (uint64_t start = 0; start < tiles; start += chunk) {
     a.blk0 = blk0 + start * tile;
-    const uint64_t grid = (tiles - start < chunk) ? tiles - start : chunk;
-    int e = launch_fill(dist, dtype, sh.wg, sh.spl, trace, grid, a, stream);
+    a.tiles = (uint32_t)((tiles - start < chunk) ? tiles - start : chunk);
+    a.chunk = sh.chunk;
+    int e = launch_fill(dist, dtype, sh.wg, sh.spl, trace, a, stream);
     if (e != 0)
       return fail(ZIG_EHIP, std::string("fill launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
   }

@@ -1,7 +1,11 @@
 // Device-side pieces of the modified ziggurat sampler for gfx950: the
 // Philox4x32-10 uniform source, the per-output slow stream, the alias draw
-// and the rejection/tail paths.  The fast path lives in the kernels, which
-// keep its table in LDS.
+// and the rejection/tail paths.  The fast path lives in the kernels.
+//
+// The slow paths read their tables through a TabView, a set of pointers
+// that the kernels aim at LDS copies (the hot region, box and alias tables)
+// or at the device tables (the rarely used ones); every function here is
+// inlined so the compiler sees which address space each pointer lives in.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,8 +29,9 @@ __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t a = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t b = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    // three-input xor in one v_bitop3_b32 (truth table 0x96)
+    const uint32_t a = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+    const uint32_t b = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = a;
@@ -63,11 +68,41 @@ struct SlowStream {
   }
 };
 
+// Tables of one distribution as the slow paths read them.  X[L] = 0 and
+// f[L] = 1; box j spans [X[j], X[j-1]] x [f[j-1], f[j]], its width and
+// height being the same double subtractions the table builder defines.
+struct TabView {
+  const double* X;
+  const double* f;
+  const uint64_t* T;
+  const uint32_t* A;
+  const double* XS;
+  uint32_t L, imask, b;
+  uint64_t keps;
+  double X0, invX0;
+};
+
+__device__ __forceinline__ TabView global_view(const DevTable* t) {
+  TabView v;
+  v.X = t->X;
+  v.f = t->f;
+  v.T = t->T;
+  v.A = t->A;
+  v.XS = t->XS;
+  v.L = t->L;
+  v.imask = t->i_max - 1;
+  v.b = t->b;
+  v.keps = t->K_eps;
+  v.X0 = t->X0;
+  v.invX0 = t->invX0;
+  return v;
+}
+
 // Region draw: column c from the low b bits, compare the high 64-b bits
 // with the column threshold, else take the column's alias.
-__device__ __forceinline__ uint32_t alias_region(const DevTable* tb, uint64_t r) {
-  const uint32_t c = (uint32_t)r & (tb->i_max - 1);
-  return (r >> tb->b) < tb->T[c] ? c : tb->A[c];
+__device__ __forceinline__ uint32_t alias_region(const TabView& v, uint64_t r) {
+  const uint32_t c = (uint32_t)r & v.imask;
+  return (r >> v.b) < v.T[c] ? c : v.A[c];
 }
 
 __device__ __forceinline__ double lattice53(uint64_t k) { return (double)k * 0x1p-53; }
@@ -78,7 +113,7 @@ __device__ __forceinline__ double lattice53(uint64_t k) { return (double)k * 0x1
 // level, innermost first); a box is sampled by reflection across the chord,
 // the eps band shortcut and the exact test, retrying in the same box.
 // `first_region` receives the first j drawn, `tests` counts exp() calls.
-__device__ __noinline__ double exp_slow(const DevTable* E, SlowStream& s, int32_t& first_region, uint32_t& tests) {
+__device__ __forceinline__ double exp_slow(const TabView& E, SlowStream& s, int32_t& first_region, uint32_t& tests) {
   uint32_t nest = 0;
   double y = 0.0;
   bool first = true;
@@ -91,15 +126,16 @@ __device__ __noinline__ double exp_slow(const DevTable* E, SlowStream& s, int32_
     if (j == 0) {
       ++nest;
       const uint64_t w = s.next();
-      const uint32_t i = (uint32_t)w & (E->i_max - 1);
-      if (i < E->L) {
-        y = (double)(w >> 11) * E->XS[i];
+      const uint32_t i = (uint32_t)w & E.imask;
+      if (i < E.L) {
+        y = (double)(w >> 11) * E.XS[i];
         break;
       }
       continue;
     }
-    const double left = E->X[j], width = E->W[j], height = E->H[j], base = E->f[j - 1];
-    const uint64_t keps = E->K_eps;
+    const double left = E.X[j], right = E.X[j - 1];
+    const double base = E.f[j - 1], top = E.f[j];
+    const double width = right - left, height = top - base;
     for (;;) {
       uint64_t k1 = s.next() >> 11;
       uint64_t k2 = s.next() >> 11;
@@ -109,7 +145,7 @@ __device__ __noinline__ double exp_slow(const DevTable* E, SlowStream& s, int32_
         k1 = r1;
       }
       const double x = __builtin_fma(lattice53(k1), width, left);
-      if (k1 + k2 <= keps) {
+      if (k1 + k2 <= E.keps) {
         y = x;
         break;
       }
@@ -122,14 +158,14 @@ __device__ __noinline__ double exp_slow(const DevTable* E, SlowStream& s, int32_
     }
     break;
   }
-  for (uint32_t c = 0; c < nest; ++c) y = E->X0 + y;
+  for (uint32_t c = 0; c < nest; ++c) y = E.X0 + y;
   return y;
 }
 
 // The whole exponential sampler started from fast word w.
-__device__ __forceinline__ double exp_from_word(const DevTable* E, uint64_t w, SlowStream& s, uint32_t& tests) {
-  const uint32_t i = (uint32_t)w & (E->i_max - 1);
-  if (i < E->L) return (double)(w >> 11) * E->XS[i];
+__device__ __forceinline__ double exp_from_word(const TabView& E, uint64_t w, SlowStream& s, uint32_t& tests) {
+  const uint32_t i = (uint32_t)w & E.imask;
+  if (i < E.L) return (double)(w >> 11) * E.XS[i];
   int32_t unused;
   return exp_slow(E, s, unused, tests);
 }
@@ -138,19 +174,21 @@ __device__ __forceinline__ double exp_from_word(const DevTable* E, uint64_t w, S
 // Marsaglia's method with two exponential draws E1, E2 (t = E1 / X_0,
 // accept when 2 E2 > t^2, return X_0 + t); a box is sampled by plain
 // rejection against e^{-x^2/2}, retrying in the same box.
-__device__ __noinline__ double normal_slow(const DevTable* N, const DevTable* E, SlowStream& s, int32_t& first_region,
-                                           uint32_t& tests) {
+__device__ __forceinline__ double normal_slow(const TabView& N, const TabView& E, SlowStream& s,
+                                              int32_t& first_region, uint32_t& tests) {
   const uint32_t j = alias_region(N, s.next());
   first_region = (int32_t)j;
   if (j == 0) {
     for (;;) {
       const double e1 = exp_from_word(E, s.next(), s, tests);
       const double e2 = exp_from_word(E, s.next(), s, tests);
-      const double t = e1 * N->invX0;
-      if (e2 + e2 > t * t) return N->X0 + t;
+      const double t = e1 * N.invX0;
+      if (e2 + e2 > t * t) return N.X0 + t;
     }
   }
-  const double left = N->X[j], width = N->W[j], height = N->H[j], base = N->f[j - 1];
+  const double left = N.X[j], right = N.X[j - 1];
+  const double base = N.f[j - 1], top = N.f[j];
+  const double width = right - left, height = top - base;
   for (;;) {
     const uint64_t k1 = s.next() >> 11;
     const uint64_t k2 = s.next() >> 11;
@@ -161,19 +199,40 @@ __device__ __noinline__ double normal_slow(const DevTable* N, const DevTable* E,
   }
 }
 
-// Magnitude of output g on its slow path.
+// Magnitude of output g on its slow path.  `own` is the distribution's
+// table view, `ex` the exponential one (the normal tail).
 template <uint32_t DIST>
-__device__ __forceinline__ double slow_magnitude(const DevTable* tab, const DevTable* etab, uint64_t g, uint32_t k0,
+__device__ __forceinline__ double slow_magnitude(const TabView& own, const TabView& ex, uint64_t g, uint32_t k0,
                                                  uint32_t k1, int32_t& region, uint32_t& words, uint32_t& tests) {
   SlowStream s(g, k0, k1);
   tests = 0;
   double m;
   if constexpr (DIST == kDistExp)
-    m = exp_slow(tab, s, region, tests);
+    m = exp_slow(own, s, region, tests);
   else
-    m = normal_slow(tab, etab, s, region, tests);
+    m = normal_slow(own, ex, s, region, tests);
   words = s.t;
   return m;
+}
+
+// Sign of normal output g (FP64: bit 10 of its fast word; FP32: bit 8),
+// recomputed from its fast block for the rare outputs on the slow path.
+template <uint32_t DT>
+__device__ __forceinline__ bool normal_sign(uint64_t g, uint32_t k0, uint32_t k1) {
+  if constexpr (DT == kF64) {
+    const uint64_t m = g >> 1;
+    uint32_t c0 = (uint32_t)m, c1 = (uint32_t)(m >> 32), c2 = 0u, c3 = 0u;
+    philox10(c0, c1, c2, c3, k0, k1);
+    const uint32_t lo = (g & 1) ? c2 : c0;
+    return (lo >> 10) & 1u;
+  } else {
+    const uint64_t m = g >> 2;
+    uint32_t c0 = (uint32_t)m, c1 = (uint32_t)(m >> 32), c2 = 0u, c3 = 1u;
+    philox10(c0, c1, c2, c3, k0, k1);
+    const uint32_t r = g & 3;
+    const uint32_t w = r == 0 ? c0 : r == 1 ? c1 : r == 2 ? c2 : c3;
+    return (w >> 8) & 1u;
+  }
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {

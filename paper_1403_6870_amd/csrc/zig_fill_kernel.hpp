@@ -1,0 +1,326 @@
+// The fill kernel of the modified ziggurat sampler for gfx950.
+//
+// Work is cut into tiles of WG * S consecutive Philox blocks (2 FP64 or 4
+// FP32 outputs per block), each written contiguously by one workgroup.  A
+// workgroup first copies the fast-path table X_i 2^-53 and the slow-path
+// tables (X, f, alias) of its distribution into LDS.  Per tile:
+//   A. every lane computes S blocks.  Each output takes its layer index and
+//      magnitude from its fast word; when the layer lies under the density
+//      (i < L, Table 1 step 2) its value is one multiply plus the
+//      location-scale epilogue.  Values go to an LDS staging tile; for each
+//      output slot the wave's ballot of slow lanes (i >= L) is written to an
+//      LDS bitmap.
+//   B. the slow outputs are numbered by prefix sums over the bitmap words
+//      and shared out over all lanes: region draw, overhang box or tail
+//      (Table 1 steps 3-8) on the output's own slow stream, tables from
+//      LDS (a normal output's sign is re-derived from its fast block); each
+//      result overwrites its staging place.
+//   C. every lane copies its blocks from LDS to HBM with 16-byte stores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "zig_device.hpp"
+
+namespace zig {
+
+template <uint32_t DT>
+struct OutType;
+template <>
+struct OutType<kF64> {
+  using T = double;
+  using V = double2;
+  static constexpr int per_block = 2;
+};
+template <>
+struct OutType<kF32> {
+  using T = float;
+  using V = float4;
+  static constexpr int per_block = 4;
+};
+
+template <uint32_t DT, int WG, int S>
+struct FillShape {
+  using OutT = typename OutType<DT>::T;
+  using VecT = typename OutType<DT>::V;
+  static constexpr int O = OutType<DT>::per_block;
+  static constexpr int TILE = WG * S;
+  static constexpr int NWAVE = WG / 64;
+  static constexpr int NWORD = S * O * NWAVE;  // one 64-bit ballot word per (s, o, wave)
+  static_assert(WG % 64 == 0 && NWORD <= 1024 && TILE * 16 <= 32768, "tile shape");
+};
+
+// LDS of one workgroup
+template <uint32_t DT, int WG, int S>
+struct FillLds {
+  using Sh = FillShape<DT, WG, S>;
+  typename Sh::OutT xs[kMaxLayers];
+  double X[kMaxLayers + 1];
+  double f[kMaxLayers + 1];
+  uint64_t T[kMaxLayers];
+  uint32_t A[kMaxLayers];
+  typename Sh::VecT stage[Sh::TILE];
+  uint64_t slowmap[Sh::NWORD];
+  uint32_t prefix[Sh::NWORD + 1];
+  uint32_t tile;
+};
+
+// Per-workgroup constants of one fill.
+struct FillCtx {
+  dev::TabView own, ex;
+  uint32_t k0, k1;
+  double scale, shift;
+};
+
+template <uint32_t DIST, uint32_t DT, int WG, int S>
+__device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG, S>& sh) {
+  const DevTable* tb = a.tab;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < kMaxLayers; i += WG) {
+    if constexpr (DT == kF64)
+      sh.xs[i] = tb->XS[i];
+    else
+      sh.xs[i] = tb->XS32[i];
+    sh.T[i] = tb->T[i];
+    sh.A[i] = tb->A[i];
+  }
+  for (uint32_t i = tid; i <= kMaxLayers; i += WG) {
+    sh.X[i] = tb->X[i];
+    sh.f[i] = tb->f[i];
+  }
+  FillCtx c;
+  c.own = dev::global_view(tb);
+  c.own.X = sh.X;
+  c.own.f = sh.f;
+  c.own.T = sh.T;
+  c.own.A = sh.A;
+  if constexpr (DT == kF64) c.own.XS = sh.xs;
+  c.ex = dev::global_view(a.etab);
+  c.k0 = (uint32_t)a.seed;
+  c.k1 = (uint32_t)(a.seed >> 32);
+  c.scale = a.scale;
+  c.shift = a.shift;
+  return c;
+}
+
+// One tile (tile index t of this launch).  Ends with the staging tile
+// written out; callers separate consecutive tiles with a barrier.
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE>
+__device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, FillLds<DT, WG, S>& sh,
+                                          uint32_t t) {
+  using Sh = FillShape<DT, WG, S>;
+  using OutT = typename Sh::OutT;
+  using VecT = typename Sh::VecT;
+  constexpr int O = Sh::O;
+  constexpr int NWAVE = Sh::NWAVE;
+  constexpr int NWORD = Sh::NWORD;
+  constexpr int TILE = Sh::TILE;
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t wave = tid >> 6;
+  const uint32_t L = c.own.L;
+  const uint32_t imask = c.own.imask;
+  const float fscale = (float)c.scale, fshift = (float)c.shift;
+  OutT* const out = static_cast<OutT*>(a.out);
+  OutT* const stage_s = reinterpret_cast<OutT*>(sh.stage);
+
+  const uint64_t tile0 = a.blk0 + (uint64_t)t * TILE;
+  const bool interior = a.has_full && tile0 >= a.full_lo && tile0 + (TILE - 1) <= a.full_hi;
+
+  // A: fast path into the staging tile, slow outputs into the bitmap
+  auto phase_a = [&](auto interior_tag) {
+    constexpr bool IN = decltype(interior_tag)::value;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;
+      uint32_t c0 = (uint32_t)m, c1 = (uint32_t)(m >> 32), c2 = 0u, c3 = (DT == kF64) ? 0u : 1u;
+      dev::philox10(c0, c1, c2, c3, c.k0, c.k1);
+      OutT v[O];
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        const uint64_t g = m * O + o;
+        bool live = true;
+        if constexpr (!IN) live = (m <= a.blk_last) && (g >= a.first) && (g <= a.last);
+        uint32_t i;
+        OutT x;
+        if constexpr (DT == kF64) {
+          const uint64_t w =
+              (o == 0) ? ((uint64_t)c0 | ((uint64_t)c1 << 32)) : ((uint64_t)c2 | ((uint64_t)c3 << 32));
+          i = (uint32_t)w & imask;
+          x = (double)(w >> 11) * sh.xs[i];
+          if constexpr (DIST == kDistNormal) {
+            if ((w >> 10) & 1u) x = -x;
+          }
+        } else {
+          const uint32_t w = (o == 0) ? c0 : (o == 1) ? c1 : (o == 2) ? c2 : c3;
+          i = w & imask;
+          if constexpr (DIST == kDistExp) {
+            x = (float)(w >> 8) * sh.xs[i];
+          } else {
+            x = (float)(w >> 9) * sh.xs[i];
+            if ((w >> 8) & 1u) x = -x;
+          }
+        }
+        // a slow output's value here is a placeholder that phase B replaces
+        const bool slow = live && (i >= L);
+        if constexpr (DT == kF64)
+          v[o] = __builtin_fma(c.scale, x, c.shift);
+        else
+          v[o] = __builtin_fmaf(fscale, x, fshift);
+        const uint64_t mask = __ballot(slow);
+        if (lane == 0) sh.slowmap[(s * O + o) * NWAVE + wave] = mask;
+        if constexpr (TRACE) {
+          if (live) {
+            const uint64_t k = g - a.first;
+            if (a.t_layer) a.t_layer[k] = i;
+            if (!slow) {
+              if (a.t_region) a.t_region[k] = -1;
+              if (a.t_words) a.t_words[k] = 0;
+              if (a.t_tests) a.t_tests[k] = 0;
+            }
+          }
+        }
+      }
+      VecT vv;
+      if constexpr (DT == kF64) {
+        vv.x = v[0];
+        vv.y = v[1];
+      } else {
+        vv.x = v[0];
+        vv.y = v[1];
+        vv.z = v[2];
+        vv.w = v[3];
+      }
+      sh.stage[s * WG + tid] = vv;
+    }
+  };
+  if (interior)
+    phase_a(std::true_type());
+  else
+    phase_a(std::false_type());
+  __syncthreads();
+
+  // B: number the slow outputs (exclusive prefix over the bitmap words, by
+  // wave 0) and share them out over every lane
+  if (wave == 0) {
+    constexpr int PER = (NWORD + 63) / 64;
+    uint32_t cnt[PER];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int w = lane * PER + k;
+      cnt[k] = (w < NWORD) ? (uint32_t)__popcll(sh.slowmap[w]) : 0u;
+      mine += cnt[k];
+    }
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t up = __shfl_up(incl, d);
+      if ((int)lane >= d) incl += up;
+    }
+    uint32_t run = incl - mine;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int w = lane * PER + k;
+      if (w < NWORD) sh.prefix[w] = run;
+      run += cnt[k];
+    }
+    if (lane == 63) sh.prefix[NWORD] = incl;
+  }
+  __syncthreads();
+  const uint32_t total = sh.prefix[NWORD];
+  for (uint32_t e = tid; e < total; e += WG) {
+    // the word holding entry e: prefix[lo] <= e < prefix[lo + 1]
+    uint32_t lo = 0, hi = NWORD;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (sh.prefix[mid] <= e)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    uint64_t bits = sh.slowmap[lo];
+    for (uint32_t r = e - sh.prefix[lo]; r > 0; --r) bits &= bits - 1;
+    const uint32_t ln = (uint32_t)__ffsll((unsigned long long)bits) - 1;
+    const uint32_t so = lo / NWAVE, wv = lo % NWAVE;
+    const uint32_t s = so / O, o = so % O;
+    const uint32_t blk = s * WG + wv * 64 + ln;
+    const uint64_t g = (tile0 + blk) * O + o;
+    OutT* place = stage_s + blk * O + o;
+    bool neg = false;
+    if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, c.k0, c.k1);
+    int32_t region;
+    uint32_t words, tests;
+    const double mag = dev::slow_magnitude<DIST>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
+    OutT x = (OutT)mag;
+    if (neg) x = -x;
+    if constexpr (DT == kF64)
+      *place = __builtin_fma(c.scale, x, c.shift);
+    else
+      *place = __builtin_fmaf(fscale, x, fshift);
+    if constexpr (TRACE) {
+      const uint64_t k = g - a.first;
+      if (a.t_region) a.t_region[k] = region;
+      if (a.t_words) a.t_words[k] = words;
+      if (a.t_tests) a.t_tests[k] = tests;
+    }
+  }
+  __syncthreads();
+
+  // C: staging tile to HBM
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;
+    const uint64_t g0 = m * O;
+    const VecT vv = sh.stage[s * WG + tid];
+    if (interior || (m <= a.blk_last && g0 >= a.first && g0 + (O - 1) <= a.last)) {
+      if (a.aligned16) {
+        *reinterpret_cast<VecT*>(out + (g0 - a.first)) = vv;
+      } else {
+        const OutT* pv = reinterpret_cast<const OutT*>(&vv);
+#pragma unroll
+        for (int o = 0; o < O; ++o) out[g0 + o - a.first] = pv[o];
+      }
+    } else if (m <= a.blk_last) {
+      const OutT* pv = reinterpret_cast<const OutT*>(&vv);
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        const uint64_t g = g0 + o;
+        if (g >= a.first && g <= a.last) out[g - a.first] = pv[o];
+      }
+    }
+  }
+}
+
+// Persistent workgroups: each takes `a.chunk` consecutive tiles per atomic
+// step of the per-stream counter (one atomic per tile would serialise the
+// device on that address), so the tiles in flight stay a window that
+// sweeps through the output in address order.  The last workgroup to leave
+// resets the counters for the next launch on the same stream.
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE>
+__global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
+  __shared__ FillLds<DT, WG, S> sh;
+  const FillCtx c = load_tables<DIST, DT, WG, S>(a, sh);
+  for (;;) {
+    if (threadIdx.x == 0) sh.tile = atomicAdd(&a.counters[0], 1u);
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)sh.tile * a.chunk;
+    if (t0 >= a.tiles) break;
+    const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
+    for (uint64_t t = t0; t < t1; ++t) {
+      fill_tile<DIST, DT, WG, S, TRACE>(a, c, sh, (uint32_t)t);
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (atomicAdd(&a.counters[1], 1u) == gridDim.x - 1) {
+      atomicExch(&a.counters[0], 0u);
+      atomicExch(&a.counters[1], 0u);
+    }
+  }
+}
+
+}  // namespace zig

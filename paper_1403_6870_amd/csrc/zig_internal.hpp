@@ -59,8 +59,12 @@ struct FillArgs {
   double scale, shift;
   const DevTable* tab;   // tables of the distribution
   const DevTable* etab;  // exponential tables (normal tail)
-  uint32_t queue;        // LDS queue capacity
+  uint32_t* counters;    // [0] next tile, [1] workgroups done; zero between launches
+  uint32_t tiles;        // tiles of WG * S blocks in this launch
+  uint32_t chunk;        // tiles taken per step of the counter
   uint32_t aligned16;    // 16-byte block stores are aligned
+  uint32_t has_full;     // some block has all its outputs in range
+  uint64_t full_lo, full_hi;  // first and last such block
   // trace arrays (trace build only), indexed by output - first
   uint32_t* t_layer;
   int32_t* t_region;
@@ -68,9 +72,10 @@ struct FillArgs {
   uint32_t* t_tests;
 };
 
-// Launch of one (dist, dtype, wg, spl) variant; defined in zig_fill.hip.
+// Launch of one (dist, dtype, wg, spl) variant over a.tiles tiles, with as
+// many persistent workgroups as fit on the device; defined in zig_fill.hip.
 // Returns 0 or a hipError_t value.
-int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, uint64_t grid,
-                const FillArgs& a, void* stream);
+int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, const FillArgs& a,
+                void* stream);
 
 }  // namespace zig

@@ -6,9 +6,9 @@
 namespace zig {
 
 struct Shape {
-  uint32_t wg;     // lanes per workgroup
+  uint32_t wg;   // lanes per workgroup
   uint32_t spl;    // Philox blocks per lane per tile
-  uint32_t queue;  // slow-lane queue capacity per workgroup
+  uint32_t chunk;  // tiles per step of the tile counter
 };
 
 // shapes compiled into the library
@@ -16,9 +16,5 @@ bool shape_supported(uint32_t wg, uint32_t spl);
 
 // shape for a fill of n outputs (tuned table, else the built-in default)
 Shape tuned_shape(uint32_t dist, uint32_t dtype, uint64_t n);
-
-// default queue capacity for a tile of `outputs` outputs: about three
-// times the expected number of slow outputs at 256 layers
-uint32_t default_queue(uint64_t outputs);
 
 }  // namespace zig

@@ -17,7 +17,6 @@ LIB_PATH = os.path.join(HERE, "libzig.so")
 
 ZIG_OK, ZIG_EINVAL, ZIG_ENOTABLES, ZIG_EHIP, ZIG_ENOMEM, ZIG_EBUSY, ZIG_ESTATE = range(7)
 EXP, NORMAL = 0, 1
-QUEUE_NONE = 0xFFFFFFFF
 F64, F32 = 0, 1
 
 if not os.path.exists(LIB_PATH):
@@ -43,7 +42,7 @@ class TableView(ctypes.Structure):
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("i_max", u32), ("wg", u32), ("spl", u32), ("queue", u32)]
+    _fields_ = [("i_max", u32), ("wg", u32), ("spl", u32)]
 
 
 def _sig(name, res, args):
@@ -85,8 +84,7 @@ def _launch(launch):
         return None
     if isinstance(launch, Launch):
         return ctypes.byref(launch)
-    return ctypes.byref(Launch(launch.get("i_max", 0), launch.get("wg", 0), launch.get("spl", 0),
-                               launch.get("queue", 0)))
+    return ctypes.byref(Launch(launch.get("i_max", 0), launch.get("wg", 0), launch.get("spl", 0)))
 
 
 def zig_build_tables(i_max=256):

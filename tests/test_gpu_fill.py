@@ -13,7 +13,7 @@ from helpers import EXP, F32, F64, NORMAL, gpu_fill, oracle_fill, parity, to_np
 pytestmark = pytest.mark.gpu
 
 ULP = {F64: 4, F32: 2}
-ZIG_LAUNCH_SHAPES = [(w, s) for w in (64, 128, 256, 512) for s in (1, 2, 4, 8)]
+ZIG_LAUNCH_SHAPES = [(w, s) for w in (64, 128, 256, 512) for s in (1, 2, 4, 8) if w * s <= 2048]
 
 
 @pytest.fixture(scope="module")
@@ -84,17 +84,16 @@ def test_trace_parity(O, torch_cuda, dist, dtype, i_max):
 @pytest.mark.parametrize("dtype", [F64, F32])
 @pytest.mark.parametrize("dist", [EXP, NORMAL])
 def test_launch_shape_independence(torch_cuda, dist, dtype, i_max):
-    """Every compiled workgroup size x blocks-per-lane and queue capacities
-    from 0 (all slow work done in place) up give the same bits."""
+    """Every compiled workgroup size x blocks-per-lane (tile and slow-queue
+    depth) gives the same bits."""
     n = 3 * 512 * 8 * 4 + 1001
     p0, p1 = (0.7, 0.0) if dist == EXP else (0.5, 2.0)
     ref = to_np(gpu_fill(dist, dtype, 99, 3, n, p0, p1, launch={"i_max": i_max}))
     it = np.int64 if dtype == F64 else np.int32
     for wg, spl in ZIG_LAUNCH_SHAPES:
-        for q in (0xFFFFFFFF, 1, 7, 64, 4096):
-            launch = {"i_max": i_max, "wg": wg, "spl": spl, "queue": q}
-            got = to_np(gpu_fill(dist, dtype, 99, 3, n, p0, p1, launch=launch))
-            assert np.array_equal(got.view(it), ref.view(it)), (wg, spl, q)
+        launch = {"i_max": i_max, "wg": wg, "spl": spl}
+        got = to_np(gpu_fill(dist, dtype, 99, 3, n, p0, p1, launch=launch))
+        assert np.array_equal(got.view(it), ref.view(it)), (wg, spl)
 
 
 @pytest.mark.parametrize("dtype", [F64, F32])
