@@ -21,6 +21,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# HBM bytes per launch of the normal FP64 fill kernel (2^30 outputs) from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by the ratio of the known
+# bytes of a 1 GiB device copy to what the same counter read for it; the
+# commands and raw readings are in profiles/fill_kernel_counters.txt.
+# Reset to None whenever the fill kernel changes until it is re-measured.
+TRAFFIC = 8594787680
 N_C3 = 1 << 30
 N_C2 = 1 << 28
 
@@ -82,6 +88,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 1 GiB (a kernel of known traffic, for scaling the "
+                         "HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler shards by index range with no exchange step, "
@@ -109,13 +118,22 @@ def main():
     samples = 2 * N_C3 * args.steps
     value = samples / wall / 1e9
     d = np.array(durs)
-    avg_ms = float(d.mean())
+    avg_ms = float(d[:, 1].mean())  # the normal fill, the dominant kernel
     bytes_per_launch = N_C3 * 8
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    log("headline: %.2f Gsamples/s, fill kernel %.3f ms avg (exp %.3f, normal %.3f), %.0f GB/s" %
-        (value, avg_ms, d[:, 0].mean(), d[:, 1].mean(), achieved))
+    log("headline: %.2f Gsamples/s; fill kernel exp %.3f ms, normal %.3f ms (%.0f GB/s)" %
+        (value, d[:, 0].mean(), d[:, 1].mean(), achieved))
     del out_e, out_n
     torch.cuda.empty_cache()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
+        torch.cuda.empty_cache()
 
     result = {
         "metric": "Gsamples/s FP64 exp+normal & % HBM-write roofline; batched p50/p99 latency",
@@ -126,10 +144,12 @@ def main():
                                "256 layers, one launch each, output resident in HBM",
                    "samples_per_step": 2 * N_C3, "bytes_written_per_step": 2 * N_C3 * 8},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "fill_kernel (FP64, exp and normal launches averaged)",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC,
+                     "kernel": "fill_kernel<normal, FP64> (the longer of the two launches of a step)",
+                     "bytes_per_launch": bytes_per_launch,
                      "per_launch_ms": {"exp": round(float(d[:, 0].mean()), 4),
-                                       "normal": round(float(d[:, 1].mean()), 4)}},
+                                       "normal": round(float(d[:, 1].mean()), 4)},
+                     "exp_fill_GB/s": round(bytes_per_launch / (float(d[:, 0].mean()) * 1e-3) / 1e9, 1)},
     }
 
     if not args.no_extra:

@@ -117,7 +117,7 @@ int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dt
                     void* out, void* stream);
 
 /* Launch shape and table size for zig_fill.  Zero fields mean "pick":
- * i_max 256; wg/spl from the tuned table.  wg in {64,128,256,512} lanes
+ * i_max 256; wg/spl from the tuned table.  wg in {64,...,1024} lanes
  * per workgroup and spl in {1,2,4,8} Philox blocks per lane make a tile
  * of wg * spl blocks (at most 2048), which is also the depth of the
  * per-workgroup slow-output queue. */

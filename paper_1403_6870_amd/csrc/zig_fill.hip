@@ -64,6 +64,7 @@ int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
     ZIG_SHAPE(128, 1) ZIG_SHAPE(128, 2) ZIG_SHAPE(128, 4) ZIG_SHAPE(128, 8)
     ZIG_SHAPE(256, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4) ZIG_SHAPE(256, 8)
     ZIG_SHAPE(512, 1) ZIG_SHAPE(512, 2) ZIG_SHAPE(512, 4)
+    ZIG_SHAPE(1024, 1) ZIG_SHAPE(1024, 2)
   } else {
     ZIG_SHAPE(64, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4)
   }

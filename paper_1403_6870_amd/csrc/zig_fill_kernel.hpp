@@ -164,13 +164,22 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, F
             if ((w >> 8) & 1u) x = -x;
           }
         }
-        // a slow output's value here is a placeholder that phase B replaces
+        // a slow output's value here is a placeholder that phase B replaces;
+        // for the exponential the shift is +0 and x >= 0, where
+        // fma(scale, x, +0) is the rounded product
         const bool slow = live && (i >= L);
-        if constexpr (DT == kF64)
-          v[o] = __builtin_fma(c.scale, x, c.shift);
-        else
-          v[o] = __builtin_fmaf(fscale, x, fshift);
-        const uint64_t mask = __ballot(slow);
+        if constexpr (DIST == kDistExp) {
+          if constexpr (DT == kF64)
+            v[o] = c.scale * x;
+          else
+            v[o] = fscale * x;
+        } else {
+          if constexpr (DT == kF64)
+            v[o] = __builtin_fma(c.scale, x, c.shift);
+          else
+            v[o] = __builtin_fmaf(fscale, x, fshift);
+        }
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(slow);
         if (lane == 0) sh.slowmap[(s * O + o) * NWAVE + wave] = mask;
         if constexpr (TRACE) {
           if (live) {
@@ -257,10 +266,17 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, F
     const double mag = dev::slow_magnitude<DIST>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
     OutT x = (OutT)mag;
     if (neg) x = -x;
-    if constexpr (DT == kF64)
-      *place = __builtin_fma(c.scale, x, c.shift);
-    else
-      *place = __builtin_fmaf(fscale, x, fshift);
+    if constexpr (DIST == kDistExp) {
+      if constexpr (DT == kF64)
+        *place = c.scale * x;
+      else
+        *place = fscale * x;
+    } else {
+      if constexpr (DT == kF64)
+        *place = __builtin_fma(c.scale, x, c.shift);
+      else
+        *place = __builtin_fmaf(fscale, x, fshift);
+    }
     if constexpr (TRACE) {
       const uint64_t k = g - a.first;
       if (a.t_region) a.t_region[k] = region;

@@ -1,0 +1,95 @@
+"""Host-side checks of the library (no GPU needed): it loads, exports every
+symbol include/zig.h declares, builds tables bit-identical to the oracle's
+independent construction, and rejects bad arguments before touching a
+device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "zig.h")
+
+
+@pytest.fixture(scope="module")
+def zig():
+    from paper_1403_6870_amd import zig as z
+    return z
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(zig_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(zig):
+    names = declared_functions()
+    assert "zig_fill_exp" in names and "zig_fill_normal" in names and "zig_build_tables" in names
+    lib = ctypes.CDLL(zig.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert zig.zig_version().startswith("zigrand")
+
+
+@pytest.mark.parametrize("dist", [0, 1])
+@pytest.mark.parametrize("i_max", [8, 16, 32, 64, 128, 256])
+def test_tables_match_oracle(zig, O, dist, i_max):
+    """The library's binary128 construction (bracketed Newton) and the
+    oracle's (bisection) give the same doubles and integers."""
+    a = zig.zig_get_tables(dist, i_max)
+    b = O.table_arrays(dist, i_max)
+    assert a["L"] == b["L"]
+    for k in ["X", "f", "XS", "XS32", "W", "H", "q", "T", "A"]:
+        x, y = a[k], b[k]
+        assert x.shape == y.shape, k
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), k
+    for k in ["eps", "K_eps", "X0", "invX0"]:
+        assert a[k] == b[k], k
+
+
+def test_bad_table_arguments(zig):
+    for dist, i_max in [(2, 256), (0, 12), (0, 4), (1, 512), (0, 0)]:
+        with pytest.raises(zig.ZigError) as e:
+            zig.zig_get_tables(dist, i_max)
+        assert e.value.status == zig.ZIG_EINVAL
+    with pytest.raises(zig.ZigError):
+        zig.zig_build_tables(100)
+
+
+def test_fill_argument_validation(zig):
+    """Invalid arguments fail with ZIG_EINVAL and a message, before any
+    device work; n = 0 is a no-op."""
+    fake = 1 << 20  # never dereferenced: every call below fails validation
+    bad = [
+        lambda: zig.zig_fill_exp(1, 0, 10, 0, 0.0, fake),
+        lambda: zig.zig_fill_exp(1, 0, 10, 0, -1.0, fake),
+        lambda: zig.zig_fill_exp(1, 0, 10, 0, float("nan"), fake),
+        lambda: zig.zig_fill_exp(1, 0, 10, 0, float("inf"), fake),
+        lambda: zig.zig_fill_exp(1, 0, 10, 0, 5e-324, fake),
+        lambda: zig.zig_fill_exp(1, 0, 10, 2, 1.0, fake),
+        lambda: zig.zig_fill_normal(1, 0, 10, 0, 0.0, 0.0, fake),
+        lambda: zig.zig_fill_normal(1, 0, 10, 0, float("nan"), 1.0, fake),
+        lambda: zig.zig_fill_normal(1, 0, 10, 0, 0.0, float("inf"), fake),
+        lambda: zig.zig_fill_normal(1, 0, 10, 1, 0.0, -2.0, fake),
+        lambda: zig.zig_fill_exp(1, 0, 10, 0, 1.0, None),
+        lambda: zig.zig_fill_exp(1, 0, 10, 0, 1.0, fake + 4),
+        lambda: zig.zig_fill_exp(1, 0, 10, 1, 1.0, fake + 2),
+        lambda: zig.zig_fill_exp(1, 2 ** 64 - 5, 6, 0, 1.0, fake),
+        lambda: zig.zig_fill(3, 0, 1, 0, 10, 1.0, 1.0, fake),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"i_max": 100}),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 96}),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 512, "spl": 8}),
+    ]
+    for k, f in enumerate(bad):
+        with pytest.raises(zig.ZigError) as e:
+            f()
+        assert e.value.status == zig.ZIG_EINVAL, k
+        assert zig.zig_last_error() != "", k
+    # n = 0: no-op even with a null pointer
+    zig.zig_fill_exp(1, 0, 0, 0, 1.0, None)
+    zig.zig_fill_normal(1, 2 ** 64 - 1, 0, 1, 0.0, 1.0, None)
+    assert zig.zig_last_error() == ""
