@@ -59,6 +59,116 @@ def timed_fills(torch, zig, calls, steps, warmup):
     return wall, durs
 
 
+def c4_requests(count=4096):
+    """4096 requests: size floor(2^(20 U)), dist Bernoulli(1/2), exp lambda ~
+    U[0.1, 10], normal mu ~ N(0, 1), sigma ~ U[0.1, 5], FP64, seed = request
+    id, first index 0; drawn in that order per request from
+    numpy.random.default_rng(4)."""
+    rng = np.random.default_rng(4)
+    reqs = []
+    for k in range(count):
+        n = int(np.floor(2.0 ** (20.0 * rng.random())))
+        dist = int(rng.random() < 0.5)
+        if dist == 0:
+            p0, p1 = float(rng.uniform(0.1, 10.0)), 0.0
+        else:
+            p0, p1 = float(rng.normal()), float(rng.uniform(0.1, 5.0))
+        reqs.append((dist, 0, k, 0, n, p0, p1))
+    return reqs
+
+
+def batch_bench(torch, zig, reps=20):
+    """The 4096-request mixed batch: one batched launch (graph replay)
+    against the same requests as per-request launches."""
+    reqs = c4_requests()
+    offs, tot = [], 0
+    for r in reqs:
+        offs.append(tot)
+        tot += r[4] + (r[4] & 1)  # keep every output 16-byte aligned
+    samples = sum(r[4] for r in reqs)
+    arena_b = torch.empty(tot, dtype=torch.float64, device="cuda")
+    arena_e = torch.empty(tot, dtype=torch.float64, device="cuda")
+
+    def make(arena):
+        arr = (zig.Request * len(reqs))()
+        base = arena.data_ptr()
+        for k, (dist, dt, seed, first, n, p0, p1) in enumerate(reqs):
+            arr[k] = zig.Request(dist, dt, seed, first, n, p0, p1, base + 8 * offs[k])
+        return arr
+
+    rb, re_ = make(arena_b), make(arena_e)
+    st = torch.cuda.current_stream()
+    sp = st.cuda_stream
+    for _ in range(3):
+        zig.zig_fill_batch(rb, sp)
+        zig.zig_fill_each(re_, sp)
+    torch.cuda.synchronize()
+    lat, host = [], []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record(st)
+        zig.zig_fill_batch(rb, sp)
+        b.record(st)
+        host.append((time.perf_counter() - t0) * 1e3)
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+    # per-request launches on one stream: completion time of every request
+    # (events after each chunk of 64 requests), all submitted at time 0
+    per_lat, makespans = [], []
+    for _ in range(5):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(reqs) // 64 + 1)]
+        evs[0].record(st)
+        for c in range(0, len(reqs), 64):
+            chunk = (zig.Request * min(64, len(reqs) - c))(*re_[c:c + 64])
+            zig.zig_fill_each(chunk, sp)
+            evs[c // 64 + 1].record(st)
+        torch.cuda.synchronize()
+        ends = [evs[0].elapsed_time(e) for e in evs[1:]]
+        per_lat.append(np.repeat(ends, 64)[:len(reqs)])
+        makespans.append(ends[-1])
+    per_lat = np.concatenate(per_lat)
+    # per-request launches spread round-robin over 4 streams
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    torch.cuda.synchronize()
+    ms4 = []
+    for _ in range(5):
+        a = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for s_ in streams:
+            s_.wait_event(a)
+        for k in range(4):
+            sub = (zig.Request * len(range(k, len(reqs), 4)))(*[re_[i] for i in range(k, len(reqs), 4)])
+            zig.zig_fill_each(sub, streams[k].cuda_stream)
+        ends = []
+        for s_ in streams:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(s_)
+            ends.append(e)
+        torch.cuda.synchronize()
+        ms4.append(max(a.elapsed_time(e) for e in ends))
+    identical = bool(torch.equal(arena_b.view(torch.int64), arena_e.view(torch.int64)))
+    del arena_b, arena_e
+    torch.cuda.empty_cache()
+    lat = np.array(lat)
+    return {
+        "workload": "4096 requests, sizes floor(2^(20U)), 50/50 Exp(U[0.1,10]) / N(N(0,1), U[0.1,5]), FP64, "
+                    "seed = request id (numpy default_rng(4))",
+        "samples": samples, "bytes": samples * 8,
+        "batch_graph": {"p50_ms": round(float(np.percentile(lat, 50)), 4),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                        "Gsamples/s": round(samples / (float(np.median(lat)) * 1e-3) / 1e9, 2),
+                        "host_submit_ms": round(float(np.median(host)), 4),
+                        "latency_note": "every request of a batch completes with the batch"},
+        "per_request_1_stream": {"makespan_ms": round(float(np.median(makespans)), 3),
+                                 "p50_ms": round(float(np.percentile(per_lat, 50)), 3),
+                                 "p99_ms": round(float(np.percentile(per_lat, 99)), 3)},
+        "per_request_4_streams": {"makespan_ms": round(float(np.median(ms4)), 3)},
+        "speedup_vs_per_request": round(float(np.median(makespans)) / float(np.median(lat)), 2),
+        "outputs_identical": identical,
+    }
+
+
 def cpu_baseline(seconds_hint=True):
     from oracle import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
@@ -173,6 +283,9 @@ def main():
         torch.cuda.empty_cache()
         log("extra: %s" % json.dumps(extra))
         result["other_configs"] = extra
+        log("batched 4096-request workload")
+        result["batch"] = batch_bench(torch, zig)
+        log("batch: %s" % json.dumps(result["batch"]))
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

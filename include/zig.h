@@ -143,6 +143,41 @@ int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
                    double p1, void* out, uint32_t* layer, int32_t* region, uint32_t* words, uint32_t* tests,
                    void* stream, const zig_launch* launch);
 
+/* One request of a batch: dist ZIG_EXP (p0 = lambda) or ZIG_NORMAL (p0 = mu,
+ * p1 = sigma), dtype, seed, first_index, n and a caller-owned device output
+ * of n elements; the same contract as zig_fill for each request. */
+typedef struct {
+  uint32_t dist, dtype;
+  uint64_t seed, first_index, n;
+  double p0, p1;
+  void* out;
+} zig_request;
+
+/* Batch options: launch shape (0 = default) and flags. */
+#define ZIG_BATCH_NO_GRAPH 1u /* launch the copy and kernel directly instead of replaying a graph */
+typedef struct {
+  uint32_t wg, spl;
+  uint32_t flags;
+} zig_batch_opts;
+
+/* Fills `count` requests (up to 2^20) of uneven sizes, mixed distributions,
+ * dtypes and parameters in one persistent launch: the requests' tiles form
+ * one flat space that the device's workgroups take in chunks from an atomic
+ * counter.  Each request's output is bit-identical to zig_fill of the same
+ * request.  The request descriptors are copied from a ring of pinned host
+ * slots by a captured hipGraph (copy + kernel) that is replayed on `stream`;
+ * `reqs` may be reused as soon as the call returns.  Outputs of different
+ * requests must not overlap.  Requests with n = 0 are skipped; an invalid
+ * request fails the whole call with ZIG_EINVAL (its index in the message)
+ * before any device work. */
+int zig_fill_batch(const zig_request* reqs, uint32_t count, void* stream);
+int zig_fill_batch_ex(const zig_request* reqs, uint32_t count, void* stream, const zig_batch_opts* opts);
+
+/* The same requests as zig_fill_batch, launched one zig_fill per request in
+ * order on `stream` (the per-request baseline the batch is compared with).
+ * Stops at the first failing request. */
+int zig_fill_each(const zig_request* reqs, uint32_t count, void* stream);
+
 /* Message for the last non-zero status on this thread ("" if none). */
 const char* zig_last_error(void);
 

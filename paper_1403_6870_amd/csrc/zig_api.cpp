@@ -240,6 +240,7 @@ int params_for(uint32_t dist, double p0, double p1, double* scale, double* shift
   return check_params(dist, p0, p1, scale, shift);
 }
 void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
 
 }  // namespace zig
 

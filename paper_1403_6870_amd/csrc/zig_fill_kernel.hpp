@@ -67,11 +67,22 @@ struct FillLds {
   uint32_t tile;
 };
 
-// Per-workgroup constants of one fill.
+// Per-workgroup constants of one fill: table views, the fast-path table
+// (X_i 2^-53 as double for FP64, RN32(X_i) 2^-24/2^-23 as float for FP32),
+// the Philox key and the location-scale pair.
 struct FillCtx {
   dev::TabView own, ex;
+  const void* fast;
   uint32_t k0, k1;
   double scale, shift;
+};
+
+// LDS a tile works in: the staging tile (16 bytes per Philox block), the
+// slow-output bitmap and its prefix sums.
+struct TileLds {
+  void* stage;
+  uint64_t* slowmap;
+  uint32_t* prefix;
 };
 
 template <uint32_t DIST, uint32_t DT, int WG, int S>
@@ -97,6 +108,7 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
   c.own.T = sh.T;
   c.own.A = sh.A;
   if constexpr (DT == kF64) c.own.XS = sh.xs;
+  c.fast = sh.xs;
   c.ex = dev::global_view(a.etab);
   c.k0 = (uint32_t)a.seed;
   c.k1 = (uint32_t)(a.seed >> 32);
@@ -108,8 +120,7 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
 // One tile (tile index t of this launch).  Ends with the staging tile
 // written out; callers separate consecutive tiles with a barrier.
 template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE>
-__device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, FillLds<DT, WG, S>& sh,
-                                          uint32_t t) {
+__device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t) {
   using Sh = FillShape<DT, WG, S>;
   using OutT = typename Sh::OutT;
   using VecT = typename Sh::VecT;
@@ -125,7 +136,9 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, F
   const uint32_t imask = c.own.imask;
   const float fscale = (float)c.scale, fshift = (float)c.shift;
   OutT* const out = static_cast<OutT*>(a.out);
-  OutT* const stage_s = reinterpret_cast<OutT*>(sh.stage);
+  VecT* const stage = static_cast<VecT*>(sh.stage);
+  OutT* const stage_s = static_cast<OutT*>(sh.stage);
+  const OutT* const xs = static_cast<const OutT*>(c.fast);
 
   const uint64_t tile0 = a.blk0 + (uint64_t)t * TILE;
   const bool interior = a.has_full && tile0 >= a.full_lo && tile0 + (TILE - 1) <= a.full_hi;
@@ -150,7 +163,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, F
           const uint64_t w =
               (o == 0) ? ((uint64_t)c0 | ((uint64_t)c1 << 32)) : ((uint64_t)c2 | ((uint64_t)c3 << 32));
           i = (uint32_t)w & imask;
-          x = (double)(w >> 11) * sh.xs[i];
+          x = (double)(w >> 11) * xs[i];
           if constexpr (DIST == kDistNormal) {
             if ((w >> 10) & 1u) x = -x;
           }
@@ -158,9 +171,9 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, F
           const uint32_t w = (o == 0) ? c0 : (o == 1) ? c1 : (o == 2) ? c2 : c3;
           i = w & imask;
           if constexpr (DIST == kDistExp) {
-            x = (float)(w >> 8) * sh.xs[i];
+            x = (float)(w >> 8) * xs[i];
           } else {
-            x = (float)(w >> 9) * sh.xs[i];
+            x = (float)(w >> 9) * xs[i];
             if ((w >> 8) & 1u) x = -x;
           }
         }
@@ -203,7 +216,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, F
         vv.z = v[2];
         vv.w = v[3];
       }
-      sh.stage[s * WG + tid] = vv;
+      stage[s * WG + tid] = vv;
     }
   };
   if (interior)
@@ -291,7 +304,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, F
   for (int s = 0; s < S; ++s) {
     const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;
     const uint64_t g0 = m * O;
-    const VecT vv = sh.stage[s * WG + tid];
+    const VecT vv = stage[s * WG + tid];
     if (interior || (m <= a.blk_last && g0 >= a.first && g0 + (O - 1) <= a.last)) {
       if (a.aligned16) {
         *reinterpret_cast<VecT*>(out + (g0 - a.first)) = vv;
@@ -320,6 +333,10 @@ template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE>
 __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
   __shared__ FillLds<DT, WG, S> sh;
   const FillCtx c = load_tables<DIST, DT, WG, S>(a, sh);
+  TileLds tl;
+  tl.stage = sh.stage;
+  tl.slowmap = sh.slowmap;
+  tl.prefix = sh.prefix;
   for (;;) {
     if (threadIdx.x == 0) sh.tile = atomicAdd(&a.counters[0], 1u);
     __syncthreads();
@@ -327,7 +344,7 @@ __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
     if (t0 >= a.tiles) break;
     const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
     for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, WG, S, TRACE>(a, c, sh, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE>(a, c, tl, (uint32_t)t);
       __syncthreads();
     }
   }

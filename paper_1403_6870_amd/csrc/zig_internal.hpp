@@ -78,4 +78,44 @@ struct FillArgs {
 int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, const FillArgs& a,
                 void* stream);
 
+// One request of a batch as the batch kernel reads it (device memory).
+struct BatchReq {
+  uint64_t seed, first, last, blk0, blk_last, full_lo, full_hi;
+  void* out;
+  double scale, shift;
+  uint32_t dist, dtype, aligned16, has_full;
+  uint32_t tile_start;  // first tile of this request in the batch's tile space
+  uint32_t tiles;       // tiles of this request
+};
+static_assert(sizeof(BatchReq) == 104, "BatchReq layout");
+
+// Device batch buffer: a header followed by `count` requests.
+struct BatchHeader {
+  uint32_t count;        // requests (all with n > 0)
+  uint32_t total_tiles;  // tiles of all requests
+  uint32_t chunk;        // tiles per step of the counter
+  uint32_t pad;
+};
+static_assert(sizeof(BatchHeader) == 16, "BatchHeader layout");
+
+struct BatchArgs {
+  const BatchHeader* hdr;  // followed by the BatchReq array
+  const DevTable* tabs;    // [exp, normal]
+  uint32_t* counters;      // [0] next chunk, [1] workgroups done; zero between launches
+};
+
+// Batch kernel launch of one (wg, spl) variant with `grid` workgroups
+// (zig_batch.hip); returns 0 or a hipError_t value.  batch_groups gives the
+// resident workgroup count of that variant on the current device.
+int launch_batch(uint32_t wg, uint32_t spl, uint32_t grid, const BatchArgs& a, void* stream);
+
+int batch_groups(uint32_t wg, uint32_t spl, uint32_t* groups);
+bool batch_shape_supported(uint32_t wg, uint32_t spl);
+
+// Shared helpers of the C ABI implementation (zig_api.cpp).
+int device_tables_for(uint32_t i_max, const DevTable** out);
+int params_for(uint32_t dist, double p0, double p1, double* scale, double* shift);
+void set_error(const std::string& msg);
+void clear_error();
+
 }  // namespace zig

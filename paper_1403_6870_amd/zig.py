@@ -45,6 +45,18 @@ class Launch(ctypes.Structure):
     _fields_ = [("i_max", u32), ("wg", u32), ("spl", u32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("dist", u32), ("dtype", u32), ("seed", u64), ("first_index", u64), ("n", u64),
+                ("p0", dbl), ("p1", dbl), ("out", vp)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("wg", u32), ("spl", u32), ("flags", u32)]
+
+
+BATCH_NO_GRAPH = 1
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -59,11 +71,14 @@ _fill_normal = _sig("zig_fill_normal", i32, [u64, u64, u64, u32, dbl, dbl, vp, v
 _fill = _sig("zig_fill", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, ctypes.POINTER(Launch)])
 _fill_trace = _sig("zig_fill_trace", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, vp, vp, vp, vp,
                                            ctypes.POINTER(Launch)])
+_fill_batch = _sig("zig_fill_batch", i32, [ctypes.POINTER(Request), u32, vp])
+_fill_batch_ex = _sig("zig_fill_batch_ex", i32, [ctypes.POINTER(Request), u32, vp, ctypes.POINTER(BatchOpts)])
+_fill_each = _sig("zig_fill_each", i32, [ctypes.POINTER(Request), u32, vp])
 _last_error = _sig("zig_last_error", ctypes.c_char_p, [])
 _version = _sig("zig_version", ctypes.c_char_p, [])
 
 EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
-           "zig_last_error", "zig_version"]
+           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_last_error", "zig_version"]
 
 
 def zig_last_error():
@@ -124,6 +139,24 @@ def zig_fill_trace(dist, dtype, seed, first_index, n, p0, p1, out_ptr, layer_ptr
                        tests_ptr, stream_ptr, _launch(launch)))
 
 
+def zig_fill_batch(reqs, stream_ptr=None, opts=None):
+    """reqs: a ctypes array of Request (or a sequence of Request)."""
+    if not isinstance(reqs, ctypes.Array):
+        reqs = (Request * len(reqs))(*reqs)
+    if opts is None:
+        _check(_fill_batch(reqs, len(reqs), stream_ptr))
+    else:
+        if not isinstance(opts, BatchOpts):
+            opts = BatchOpts(opts.get("wg", 0), opts.get("spl", 0), opts.get("flags", 0))
+        _check(_fill_batch_ex(reqs, len(reqs), stream_ptr, ctypes.byref(opts)))
+
+
+def zig_fill_each(reqs, stream_ptr=None):
+    if not isinstance(reqs, ctypes.Array):
+        reqs = (Request * len(reqs))(*reqs)
+    _check(_fill_each(reqs, len(reqs), stream_ptr))
+
+
 # ---- torch conveniences -------------------------------------------------
 
 def _stream_ptr(stream):
@@ -181,3 +214,13 @@ def fill_trace(out, dist, seed, first_index=0, p0=1.0, p1=1.0, launch=None, stre
     zig_fill_trace(dist, _dtype_code(out), seed, first_index, n, p0, p1, out.data_ptr(), layer.data_ptr(),
                    region.data_ptr(), words.data_ptr(), tests.data_ptr(), _stream_ptr(stream), launch)
     return out, layer, region, words, tests
+
+
+def fill_batch(items, stream=None, opts=None):
+    """items: sequence of (out_tensor, dist, seed, first_index, p0, p1); all
+    filled by one batched launch."""
+    reqs = (Request * len(items))()
+    for k, (out, dist, seed, first, p0, p1) in enumerate(items):
+        _check_out(out)
+        reqs[k] = Request(dist, _dtype_code(out), seed, first, out.numel(), p0, p1, out.data_ptr())
+    zig_fill_batch(reqs, _stream_ptr(stream), opts)
