@@ -169,6 +169,95 @@ def batch_bench(torch, zig, reps=20):
     }
 
 
+def c5_trace(zig, seconds, rate=20000.0, clients=64, seed=5):
+    """Open-loop serving trace: Poisson arrivals at `rate`/s for `seconds`,
+    n = floor(2^(4 + 20U)), dist Bernoulli(1/2), exp lambda ~ U[0.1, 10],
+    normal mu ~ N(0, 1), sigma ~ U[0.1, 5], dtype FP32/FP64 50/50, client
+    uniform over 64; drawn as whole arrays in that order from
+    numpy.random.default_rng(5)."""
+    rng = np.random.default_rng(seed)
+    m = int(round(seconds * rate))
+    gaps = rng.exponential(1.0 / rate, m)
+    u = rng.random(m)
+    dist = (rng.random(m) < 0.5).astype(np.uint32)
+    lam = rng.uniform(0.1, 10.0, m)
+    mu = rng.normal(size=m)
+    sigma = rng.uniform(0.1, 5.0, m)
+    dtype = (rng.random(m) < 0.5).astype(np.uint32)
+    client = rng.integers(0, clients, m).astype(np.uint32)
+    tr = np.zeros(m, dtype=zig.TRACE_DTYPE)
+    tr["client"] = client
+    tr["dist"] = dist
+    tr["dtype"] = dtype
+    tr["n"] = np.floor(2.0 ** (4.0 + 20.0 * u)).astype(np.uint64)
+    tr["p0"] = np.where(dist == 0, lam, mu)
+    tr["p1"] = np.where(dist == 0, 0.0, sigma)
+    tr["t_arrival_ns"] = np.round(np.cumsum(gaps) * 1e9).astype(np.uint64)
+    return tr
+
+
+def serve_run(torch, zig, tr, naive, check_share=0.01):
+    """Replays `tr` through a fresh server (16 GiB cap, 64 clients, seed of
+    client c = 1000 + c); a seeded 1% of the requests are copied out and
+    re-generated alone with zig_fill at the reported first index."""
+    m = len(tr)
+    tr = tr.copy()
+    sel = np.flatnonzero(np.random.default_rng(55).random(m) < check_share)
+    es = np.where(tr["dtype"][sel] == 0, 8, 4).astype(np.uint64)
+    nbytes = tr["n"][sel] * es
+    offs = np.concatenate([[0], np.cumsum((nbytes + 255) // 256 * 256)])
+    copy_buf = torch.empty(int(offs[-1]) + 256, dtype=torch.uint8, device="cuda")
+    tr["copy_to"][sel] = copy_buf.data_ptr() + offs[:-1]
+    with zig.Server(16 << 30, clients=64, seed_base=1000, streams=4) as srv:
+        out = srv.replay(tr, naive=naive)
+        stats = srv.stats()
+    torch.cuda.synchronize()
+    ok = bool(np.all(out["status"] == 0))
+    identical = ok
+    for k, i in enumerate(sel):
+        n = int(tr["n"][i])
+        dt = torch.float64 if tr["dtype"][i] == 0 else torch.float32
+        got = copy_buf[int(offs[k]):int(offs[k]) + int(nbytes[k])].view(dt)
+        want = torch.empty(n, dtype=dt, device="cuda")
+        zig.fill(want, int(tr["dist"][i]), 1000 + int(tr["client"][i]), int(out["first_index"][i]),
+                 float(tr["p0"][i]), float(tr["p1"][i]))
+        if not torch.equal(got, want):
+            identical = False
+            break
+    del copy_buf
+    torch.cuda.empty_cache()
+    lat = (out["t_done_ns"].astype(np.int64) - out["t_arrival_ns"].astype(np.int64)) / 1e6
+    span = (int(out["t_done_ns"].max()) - int(out["t_arrival_ns"].min())) / 1e9
+    samples = float(tr["n"].sum())
+    res = {"requests": m, "all_ok": ok,
+           "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+           "max_ms": round(float(lat.max()), 4), "Gsamples/s": round(samples / span / 1e9, 3),
+           "span_s": round(span, 3), "checked": int(len(sel)), "outputs_identical": identical}
+    if not naive:
+        res["batches"] = int(stats["batches"])
+        res["mean_batch"] = round(m / max(1, stats["batches"]), 2)
+        res["max_bytes_in_use"] = int(stats["max_bytes_in_use"])
+    return res
+
+
+def serve_bench(torch, zig, seconds):
+    out = {"workload": "open-loop Poisson arrivals, n = floor(2^(4+20U)), 50/50 Exp(U[0.1,10]) / "
+                       "N(N(0,1), U[0.1,5]), FP32/FP64 50/50, 64 clients (seed 1000 + id), 16 GiB admission "
+                       "cap, 4 fill streams (numpy default_rng(5))",
+           "latency": "host time the completion is observed minus the scheduled arrival"}
+    for name, rate, secs in [("rate_20k", 20000.0, seconds), ("rate_200k", 200000.0, max(1.0, seconds / 5))]:
+        tr = c5_trace(zig, secs, rate)
+        offered = float(tr["n"].sum()) / secs / 1e9
+        log("serve %s: %d requests over %.1f s (offered %.1f Gsamples/s)" % (name, len(tr), secs, offered))
+        run = {"offered_Gsamples/s": round(offered, 3), "seconds": secs}
+        run["batched"] = serve_run(torch, zig, tr, naive=False)
+        log("serve %s batched: %s" % (name, json.dumps(run["batched"])))
+        run["naive_per_request"] = serve_run(torch, zig, tr, naive=True)
+        log("serve %s naive: %s" % (name, json.dumps(run["naive_per_request"])))
+        out[name] = run
+    return out
+
+
 def cpu_baseline(seconds_hint=True):
     from oracle import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
@@ -198,6 +287,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the 20k requests/s serving trace (the 200k/s trace runs a fifth of it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (a kernel of known traffic, for scaling the "
                          "HBM byte counters of a profiler run)")
@@ -286,6 +377,8 @@ def main():
         log("batched 4096-request workload")
         result["batch"] = batch_bench(torch, zig)
         log("batch: %s" % json.dumps(result["batch"]))
+        if args.serve_seconds > 0:
+            result["serving"] = serve_bench(torch, zig, args.serve_seconds)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

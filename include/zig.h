@@ -178,6 +178,141 @@ int zig_fill_batch_ex(const zig_request* reqs, uint32_t count, void* stream, con
  * Stops at the first failing request. */
 int zig_fill_each(const zig_request* reqs, uint32_t count, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Serving loop: continuous batching of fill requests from many clients.
+ *
+ * Each client c owns a sample stream with seed seed_base + c and a
+ * device-resident next index.  A submitted request of n samples is queued
+ * FIFO; the scheduler admits requests in arrival order while their outputs
+ * fit into an output arena of cap_bytes (256-byte granules, first fit),
+ * gives each its first index from its client's counter in admission order,
+ * and launches the admitted requests as one batch on the next free of
+ * `streams` fill streams: a copy of the batch descriptors, then the
+ * persistent batch kernel of zig_fill_batch, whose last workgroup raises
+ * the device counters to the ends of the batch's requests.  A request's
+ * samples are therefore the zig_fill output of (dist, dtype,
+ * seed_base + c, first_index, n, p0, p1) whatever else it was batched
+ * with; first_index is reported in its completion.  The output lives in
+ * the arena until the caller releases the ticket.
+ * --------------------------------------------------------------------- */
+typedef struct zig_server zig_server;
+
+#define ZIG_BACKEND_DEVICE 0u    /* the HIP path on the current device */
+#define ZIG_BACKEND_HOST_FAKE 1u /* host threads only, no device calls: the scheduler under test */
+
+/* Server configuration; zero fields take the stated defaults. */
+typedef struct {
+  uint32_t backend;         /* ZIG_BACKEND_* */
+  uint32_t streams;         /* fill streams, 1..8 (default 4); two batches in flight per stream */
+  uint32_t max_batch;       /* requests per batch, 1..4096 (default 1024) */
+  uint32_t clients;         /* client ids 0..clients-1, at most 2^20 (default 64) */
+  uint32_t window_us;       /* gathering window after the oldest queued arrival (default 0) */
+  uint32_t fake_latency_us; /* host fake: time each batch takes */
+  uint32_t fake_fail_every; /* host fake: every k-th request (count from 1) fails, 0 = never */
+  uint32_t pad;
+  uint64_t cap_bytes;       /* admission cap: bytes of admitted, unreleased outputs (required) */
+  uint64_t seed_base;       /* client c draws from seed seed_base + c */
+  void* arena;              /* device arena of cap_bytes supplied by the caller, or NULL to allocate */
+} zig_server_cfg;
+
+/* One request: dist/dtype/parameters as zig_fill (p0 = lambda, or p0 = mu,
+ * p1 = sigma), n samples, and an optional arrival timestamp
+ * (zig_server_now_ns clock) that latencies are measured from (0 = submit
+ * time). */
+typedef struct {
+  uint32_t dist, dtype;
+  uint64_t n;
+  double p0, p1;
+  uint64_t t_arrival_ns;
+} zig_spec;
+
+/* Completion record of one request.  Timestamps are zig_server_now_ns
+ * values; t_done_ns is taken when the host observes the batch's
+ * completion event. */
+typedef struct {
+  int32_t status;          /* ZIG_OK, or why the request did not run */
+  uint32_t client, dist, dtype;
+  uint64_t seed, first_index, n;
+  void* out;               /* n outputs in the arena (NULL unless status is ZIG_OK) */
+  uint64_t batch_id;
+  uint32_t batch_size, pad;
+  uint64_t t_arrival_ns, t_submit_ns, t_admit_ns, t_launch_ns, t_done_ns;
+} zig_completion;
+
+typedef struct {
+  uint64_t batches, requests, samples, failed_requests;
+  uint64_t max_inflight_batches, max_bytes_in_use;
+  uint64_t bytes_in_use, queued, inflight_batches;
+} zig_server_stats;
+
+/* Monotonic clock of the server's timestamps, in ns. */
+uint64_t zig_server_now_ns(void);
+
+/* Creates a server and starts its scheduler and completion threads.  The
+ * device backend uses the current device, allocates the arena unless one
+ * is supplied, and starts every client counter at 0.
+ * Errors: ZIG_EINVAL (bad configuration), ZIG_ENOMEM, ZIG_EHIP, ZIG_ENOTABLES. */
+int zig_server_create(const zig_server_cfg* cfg, zig_server** out);
+
+/* Queues a request of `client`; never waits for admission.  With
+ * ZIG_SUBMIT_NONBLOCK the request is refused with ZIG_EBUSY when the bytes
+ * admitted or queued would then exceed cap_bytes.  n = 0 completes at once
+ * without using an index.  *ticket identifies the request until released.
+ * Errors: ZIG_EINVAL (client out of range, bad parameters, n * element size
+ * above cap_bytes), ZIG_EBUSY, ZIG_ESTATE (server shutting down).  A request
+ * whose indices would pass 2^64 - 2 (counter + n > 2^64 - 1) completes with
+ * status ZIG_EINVAL at admission and leaves the counter where it was. */
+#define ZIG_SUBMIT_NONBLOCK 1u
+int zig_server_submit(zig_server* srv, uint32_t client, const zig_spec* spec, uint32_t flags, uint64_t* ticket);
+
+/* Waits up to timeout_us (negative: no limit) for a request and copies its
+ * completion record to *out (may be NULL).  Returns the request's status,
+ * ZIG_EBUSY on timeout, ZIG_ESTATE for an unknown ticket. */
+int zig_server_wait(zig_server* srv, uint64_t ticket, int64_t timeout_us, zig_completion* out);
+
+/* Returns a completed request's output space to the arena and forgets the
+ * ticket.  Errors: ZIG_ESTATE (unknown ticket or not complete). */
+int zig_server_release(zig_server* srv, uint64_t ticket);
+
+/* Client disconnect: its queued requests are cancelled (status ZIG_ESTATE,
+ * no index used), its completed requests are released, and its requests in
+ * flight are released when they complete.  *reclaimed (may be NULL)
+ * receives the number of requests cancelled or released. */
+int zig_server_drop_client(zig_server* srv, uint32_t client, uint64_t* reclaimed);
+
+/* Snapshot of the device counters (next index) of clients 0..count-1 once
+ * every launched batch has finished (checkpoint), and restore of them;
+ * restore needs an idle server (nothing queued or in flight).  Errors:
+ * ZIG_EINVAL, ZIG_ESTATE (restore on a busy server), ZIG_EHIP. */
+int zig_server_counters(zig_server* srv, uint64_t* next_index, uint32_t count);
+int zig_server_set_counters(zig_server* srv, const uint64_t* next_index, uint32_t count);
+
+int zig_server_stats_get(zig_server* srv, zig_server_stats* out);
+
+/* Open-loop replay of a request trace: request i is submitted at
+ * t0 + arrival_ns[i] (t0 = the call's start), its latency counted from that
+ * scheduled time, and released once complete; if copy_to[i] is not NULL its
+ * output is first copied there (device memory of n elements).  out[i]
+ * receives the completion record (its `out` field is then stale).  Blocks
+ * until every request has completed.
+ * ZIG_REPLAY_NAIVE replays the same trace on a naive server instead: each
+ * request is launched at arrival as its own zig_fill on the next of the
+ * server's fill streams (round robin), with its first index from host-side
+ * counters that start at 0, and an event per request; the batching
+ * scheduler stays idle.  Needs the device backend and an idle server. */
+#define ZIG_REPLAY_NAIVE 1u
+typedef struct {
+  uint32_t client, pad;
+  zig_spec spec;           /* spec.t_arrival_ns is the offset from t0 */
+  void* copy_to;
+} zig_trace_item;
+int zig_server_replay(zig_server* srv, const zig_trace_item* items, uint64_t count, uint32_t flags,
+                      zig_completion* out);
+
+/* Stops the server: queued requests are cancelled, batches in flight are
+ * waited for, every resource (arena included, unless supplied) is freed. */
+int zig_server_destroy(zig_server* srv);
+
 /* Message for the last non-zero status on this thread ("" if none). */
 const char* zig_last_error(void);
 

@@ -104,11 +104,20 @@ int describe(const zig_request& r, BatchReq* d, uint32_t index) {
     return fail(ZIG_EINVAL, "request " + std::to_string(index) + ": out is not aligned to its element size");
   if (r.n - 1 > UINT64_MAX - r.first_index)
     return fail(ZIG_EINVAL, "request " + std::to_string(index) + ": first_index + n exceeds 2^64");
-  const uint64_t per = r.dtype == ZIG_F64 ? 2 : 4;
+  make_descriptor(r.dist, r.dtype, r.seed, r.first_index, r.n, scale, shift, r.out, d);
+  return ZIG_OK;
+}
+
+}  // namespace
+
+void make_descriptor(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double scale,
+                     double shift, void* out, BatchReq* d) {
+  const uint64_t per = dtype == ZIG_F64 ? 2 : 4;
+  const uint64_t esize = dtype == ZIG_F64 ? 8 : 4;
   std::memset(d, 0, sizeof(*d));
-  d->seed = r.seed;
-  d->first = r.first_index;
-  d->last = r.first_index + (r.n - 1);
+  d->seed = seed;
+  d->first = first;
+  d->last = first + (n - 1);
   d->blk0 = d->first / per;
   d->blk_last = d->last / per;
   d->full_lo = d->first / per + (d->first % per != 0);
@@ -119,16 +128,24 @@ int describe(const zig_request& r, BatchReq* d, uint32_t index) {
     d->full_hi = d->last / per == 0 ? 0 : d->last / per - 1;
     d->has_full = d->last / per > 0 && d->full_lo <= d->full_hi;
   }
-  d->out = r.out;
+  d->out = out;
   d->scale = scale;
   d->shift = shift;
-  d->dist = r.dist;
-  d->dtype = r.dtype;
-  d->aligned16 = ((((uintptr_t)r.out) - d->first * esize) & 15u) == 0 ? 1u : 0u;
-  return ZIG_OK;
+  d->dist = dist;
+  d->dtype = dtype;
+  d->aligned16 = ((((uintptr_t)out) - d->first * esize) & 15u) == 0 ? 1u : 0u;
 }
 
-}  // namespace
+// About 8K blocks per counter step, and every resident workgroup gets a few
+// steps.  It travels in the header, so one graph serves every batch of a
+// size bucket; workgroups with no step to take leave at once.
+uint32_t batch_chunk(uint64_t total_tiles, uint32_t tile_blocks, uint32_t groups) {
+  uint64_t chunk = 8192 / tile_blocks;
+  if (chunk < 1) chunk = 1;
+  const uint64_t cap_chunk = total_tiles / (2ull * groups);
+  if (chunk > cap_chunk) chunk = cap_chunk < 1 ? 1 : cap_chunk;
+  return (uint32_t)chunk;
+}
 
 int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const zig_batch_opts* opts) {
   clear_error();
@@ -191,26 +208,22 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   r = ensure_capacity(s, m);
   if (r != ZIG_OK) return r;
 
-  // tiles per counter step: about 8K blocks, and every resident workgroup
-  // gets a few steps.  It travels in the header, so one graph serves every
-  // batch of a size bucket; workgroups with no step to take leave at once.
-  uint64_t chunk = 8192 / tile_blocks;
-  if (chunk < 1) chunk = 1;
-  const uint64_t cap_chunk = total / (2ull * groups);
-  if (chunk > cap_chunk) chunk = cap_chunk < 1 ? 1 : cap_chunk;
+  const uint32_t chunk = batch_chunk(total, tile_blocks, groups);
   const uint32_t grid = groups;
 
   BatchHeader* h = static_cast<BatchHeader*>(s.host);
   std::memset(h, 0, sizeof(*h));
   h->count = m;
   h->total_tiles = (uint32_t)total;
-  h->chunk = (uint32_t)chunk;
+  h->chunk = chunk;
   std::memcpy(h + 1, desc.data(), (size_t)m * sizeof(BatchReq));
 
   BatchArgs ba;
   ba.hdr = static_cast<const BatchHeader*>(s.dev);
   ba.tabs = tabs;
   ba.counters = s.counters;
+  ba.client_next = nullptr;
+  ba.seed_base = 0;
   hipStream_t st = static_cast<hipStream_t>(stream);
 
   if (flags & ZIG_BATCH_NO_GRAPH) {

@@ -9,7 +9,9 @@
 // the workgroup runs the fill's own tile code with that request's seed,
 // range, parameters and output.  Outputs are therefore bit-identical to the
 // same requests filled one by one.  Both distributions' tables are copied
-// into LDS once per workgroup.
+// into LDS once per workgroup.  For the serving loop, the last workgroup to
+// finish also advances the per-client counters (an order-free max of every
+// request's end index).
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -157,10 +159,17 @@ __global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
       __syncthreads();
     }
   }
-  if (tid == 0) {
-    if (atomicAdd(&ba.counters[1], 1u) == gridDim.x - 1) {
+  if (tid == 0) sh.req = atomicAdd(&ba.counters[1], 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (sh.req) {  // the last workgroup: every other one has taken its final step
+    if (tid == 0) {
       atomicExch(&ba.counters[0], 0u);
       atomicExch(&ba.counters[1], 0u);
+    }
+    if (ba.client_next != nullptr) {
+      for (uint32_t i = tid; i < count; i += WG)
+        atomicMax(reinterpret_cast<unsigned long long*>(&ba.client_next[reqs[i].seed - ba.seed_base]),
+                  (unsigned long long)(reqs[i].last + 1));
     }
   }
 }

@@ -102,7 +102,18 @@ struct BatchArgs {
   const BatchHeader* hdr;  // followed by the BatchReq array
   const DevTable* tabs;    // [exp, normal]
   uint32_t* counters;      // [0] next chunk, [1] workgroups done; zero between launches
+  // Serving: when not null, the last workgroup to finish raises
+  // client_next[seed - seed_base] to (last index + 1) of every request.
+  uint64_t* client_next;
+  uint64_t seed_base;
 };
+
+// Descriptor of one checked request with n > 0; the tile fields are left
+// for the caller, which knows the tile size (zig_batch.cpp).
+void make_descriptor(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double scale,
+                     double shift, void* out, BatchReq* d);
+// Tiles per step of the batch kernel's work counter.
+uint32_t batch_chunk(uint64_t total_tiles, uint32_t tile_blocks, uint32_t groups);
 
 // Batch kernel launch of one (wg, spl) variant with `grid` workgroups
 // (zig_batch.hip); returns 0 or a hipError_t value.  batch_groups gives the

@@ -57,6 +57,50 @@ class BatchOpts(ctypes.Structure):
 BATCH_NO_GRAPH = 1
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("backend", u32), ("streams", u32), ("max_batch", u32), ("clients", u32), ("window_us", u32),
+                ("fake_latency_us", u32), ("fake_fail_every", u32), ("pad", u32), ("cap_bytes", u64),
+                ("seed_base", u64), ("arena", vp)]
+
+
+class Spec(ctypes.Structure):
+    _fields_ = [("dist", u32), ("dtype", u32), ("n", u64), ("p0", dbl), ("p1", dbl), ("t_arrival_ns", u64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("status", i32), ("client", u32), ("dist", u32), ("dtype", u32), ("seed", u64),
+                ("first_index", u64), ("n", u64), ("out", vp), ("batch_id", u64), ("batch_size", u32),
+                ("pad", u32), ("t_arrival_ns", u64), ("t_submit_ns", u64), ("t_admit_ns", u64),
+                ("t_launch_ns", u64), ("t_done_ns", u64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, u64) for k in ("batches", "requests", "samples", "failed_requests", "max_inflight_batches",
+                                    "max_bytes_in_use", "bytes_in_use", "queued", "inflight_batches")]
+
+
+class TraceItem(ctypes.Structure):
+    _fields_ = [("client", u32), ("pad", u32), ("spec", Spec), ("copy_to", vp)]
+
+
+BACKEND_DEVICE, BACKEND_HOST_FAKE = 0, 1
+SUBMIT_NONBLOCK = 1
+REPLAY_NAIVE = 1
+
+# numpy views of the trace and completion arrays (same layout as the C structs)
+TRACE_DTYPE = np.dtype([("client", np.uint32), ("pad", np.uint32), ("dist", np.uint32), ("dtype", np.uint32),
+                        ("n", np.uint64), ("p0", np.float64), ("p1", np.float64), ("t_arrival_ns", np.uint64),
+                        ("copy_to", np.uint64)])
+COMPLETION_DTYPE = np.dtype([("status", np.int32), ("client", np.uint32), ("dist", np.uint32),
+                             ("dtype", np.uint32), ("seed", np.uint64), ("first_index", np.uint64),
+                             ("n", np.uint64), ("out", np.uint64), ("batch_id", np.uint64),
+                             ("batch_size", np.uint32), ("pad", np.uint32), ("t_arrival_ns", np.uint64),
+                             ("t_submit_ns", np.uint64), ("t_admit_ns", np.uint64), ("t_launch_ns", np.uint64),
+                             ("t_done_ns", np.uint64)])
+assert TRACE_DTYPE.itemsize == ctypes.sizeof(TraceItem)
+assert COMPLETION_DTYPE.itemsize == ctypes.sizeof(Completion)
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -74,11 +118,26 @@ _fill_trace = _sig("zig_fill_trace", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp
 _fill_batch = _sig("zig_fill_batch", i32, [ctypes.POINTER(Request), u32, vp])
 _fill_batch_ex = _sig("zig_fill_batch_ex", i32, [ctypes.POINTER(Request), u32, vp, ctypes.POINTER(BatchOpts)])
 _fill_each = _sig("zig_fill_each", i32, [ctypes.POINTER(Request), u32, vp])
+_srv_p = ctypes.c_void_p
+_server_now = _sig("zig_server_now_ns", u64, [])
+_server_create = _sig("zig_server_create", i32, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_srv_p)])
+_server_submit = _sig("zig_server_submit", i32, [_srv_p, u32, ctypes.POINTER(Spec), u32, ctypes.POINTER(u64)])
+_server_wait = _sig("zig_server_wait", i32, [_srv_p, u64, ctypes.c_int64, ctypes.POINTER(Completion)])
+_server_release = _sig("zig_server_release", i32, [_srv_p, u64])
+_server_drop = _sig("zig_server_drop_client", i32, [_srv_p, u32, ctypes.POINTER(u64)])
+_server_counters = _sig("zig_server_counters", i32, [_srv_p, vp, u32])
+_server_set_counters = _sig("zig_server_set_counters", i32, [_srv_p, vp, u32])
+_server_stats = _sig("zig_server_stats_get", i32, [_srv_p, ctypes.POINTER(ServerStats)])
+_server_replay = _sig("zig_server_replay", i32, [_srv_p, vp, u64, u32, vp])
+_server_destroy = _sig("zig_server_destroy", i32, [_srv_p])
 _last_error = _sig("zig_last_error", ctypes.c_char_p, [])
 _version = _sig("zig_version", ctypes.c_char_p, [])
 
 EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
-           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_last_error", "zig_version"]
+           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_server_now_ns", "zig_server_create",
+           "zig_server_submit", "zig_server_wait", "zig_server_release", "zig_server_drop_client",
+           "zig_server_counters", "zig_server_set_counters", "zig_server_stats_get", "zig_server_replay",
+           "zig_server_destroy", "zig_last_error", "zig_version"]
 
 
 def zig_last_error():
@@ -155,6 +214,100 @@ def zig_fill_each(reqs, stream_ptr=None):
     if not isinstance(reqs, ctypes.Array):
         reqs = (Request * len(reqs))(*reqs)
     _check(_fill_each(reqs, len(reqs), stream_ptr))
+
+
+def zig_server_now_ns():
+    return int(_server_now())
+
+
+class Server:
+    """Owner of a zig_server handle (the serving loop); methods mirror the
+    zig_server_* calls.  Use as a context manager or call close()."""
+
+    def __init__(self, cap_bytes, backend=BACKEND_DEVICE, streams=0, max_batch=0, clients=0, window_us=0,
+                 seed_base=0, arena_ptr=None, fake_latency_us=0, fake_fail_every=0):
+        self.cfg = ServerCfg(backend, streams, max_batch, clients, window_us, fake_latency_us, fake_fail_every, 0,
+                             cap_bytes, seed_base, arena_ptr)
+        self.clients = clients or 64
+        h = _srv_p()
+        _check(_server_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+
+    def _handle(self):
+        if self._h is None:
+            raise ZigError(ZIG_ESTATE, "server closed")
+        return self._h
+
+    def submit(self, client, dist, dtype, n, p0=1.0, p1=1.0, t_arrival_ns=0, nonblock=False):
+        spec = Spec(dist, dtype, n, p0, p1, t_arrival_ns)
+        t = u64()
+        _check(_server_submit(self._handle(), client, ctypes.byref(spec), SUBMIT_NONBLOCK if nonblock else 0,
+                              ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        """Completion record of a request; raises ZigError if it failed,
+        was cancelled or the wait timed out."""
+        c = Completion()
+        _check(_server_wait(self._handle(), ticket, timeout_us, ctypes.byref(c)))
+        return c
+
+    def poll(self, ticket, timeout_us=-1):
+        """(status, completion) without raising on the request's status."""
+        c = Completion()
+        st = _server_wait(self._handle(), ticket, timeout_us, ctypes.byref(c))
+        return st, c
+
+    def release(self, ticket):
+        _check(_server_release(self._handle(), ticket))
+
+    def drop_client(self, client):
+        n = u64()
+        _check(_server_drop(self._handle(), client, ctypes.byref(n)))
+        return n.value
+
+    def counters(self, count=None):
+        count = self.clients if count is None else count
+        a = np.zeros(count, dtype=np.uint64)
+        _check(_server_counters(self._handle(), a.ctypes.data, count))
+        return a
+
+    def set_counters(self, values):
+        a = np.ascontiguousarray(values, dtype=np.uint64)
+        _check(_server_set_counters(self._handle(), a.ctypes.data, len(a)))
+
+    def stats(self):
+        st = ServerStats()
+        _check(_server_stats(self._handle(), ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def replay(self, trace, naive=False):
+        """trace: numpy array of TRACE_DTYPE (t_arrival_ns = offset from the
+        start); returns the COMPLETION_DTYPE array."""
+        trace = np.ascontiguousarray(trace, dtype=TRACE_DTYPE)
+        out = np.zeros(len(trace), dtype=COMPLETION_DTYPE)
+        st = _server_replay(self._handle(), trace.ctypes.data, len(trace), REPLAY_NAIVE if naive else 0,
+                            out.ctypes.data)
+        if st != ZIG_OK:
+            raise ZigError(st, zig_last_error())
+        return out
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            _check(_server_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- torch conveniences -------------------------------------------------

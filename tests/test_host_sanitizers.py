@@ -1,0 +1,66 @@
+"""Host code under sanitizers (CPU only): the serving scheduler, driven on
+its host fake backend by a multi-threaded stress program, under
+ThreadSanitizer and under AddressSanitizer + UndefinedBehaviorSanitizer;
+the oracle's entry points under AddressSanitizer + UBSan.  Each program is
+built with g++/gcc from the committed sources (the library's device
+objects are linked as built, uninstrumented) and must print "ok" with no
+sanitizer report."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1403_6870_amd", "csrc")
+BUILD = os.path.join(ROOT, "paper_1403_6870_amd", "_build")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HOST = ["zig_tables.cpp", "zig_tune.cpp", "zig_api.cpp", "zig_batch.cpp", "zig_server.cpp"]
+DEVICE_OBJS = [os.path.join(BUILD, "zig_fill.hip.o"), os.path.join(BUILD, "zig_batch.hip.o")]
+
+
+def _run(cmd, **kw):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, **kw)
+    assert p.returncode == 0, "%s\n%s" % (" ".join(cmd), p.stdout[-4000:])
+    return p.stdout
+
+
+@pytest.mark.parametrize("san", ["thread", "address,undefined"])
+def test_scheduler_under_sanitizer(tmp_path, san):
+    if shutil.which("g++") is None or not all(os.path.exists(o) for o in DEVICE_OBJS):
+        pytest.skip("needs g++ and the built device objects")
+    flags = ["-O1", "-g", "-fsanitize=" + san, "-fno-omit-frame-pointer", "-std=gnu++17", "-fPIC",
+             "-ffp-contract=off", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include")]
+    objs = []
+    srcs = [os.path.join(CSRC, s) for s in HOST] + [os.path.join(ROOT, "tests", "csrc", "server_stress.cpp")]
+    procs = []
+    for src in srcs:
+        o = str(tmp_path / (os.path.basename(src) + ".o"))
+        objs.append(o)
+        procs.append(subprocess.Popen(["g++"] + flags + ["-c", src, "-o", o], stdout=subprocess.PIPE,
+                                      stderr=subprocess.STDOUT, text=True))
+    for p, src in zip(procs, srcs):
+        out = p.communicate()[0]
+        assert p.returncode == 0, "%s\n%s" % (src, out[-4000:])
+    exe = str(tmp_path / "stress")
+    _run(["g++", "-fsanitize=" + san, "-o", exe] + objs + DEVICE_OBJS +
+         ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lquadmath", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    out = _run([exe], env=env, timeout=600)
+    assert out.strip().endswith("ok"), out[-4000:]
+    assert "WARNING: ThreadSanitizer" not in out and "ERROR: AddressSanitizer" not in out
+    assert "runtime error" not in out
+
+
+def test_oracle_under_sanitizer(tmp_path):
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    exe = str(tmp_path / "oracle_san")
+    _run(["gcc", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-std=gnu11",
+          "-ffp-contract=off", "-fno-fast-math", os.path.join(ROOT, "tests", "csrc", "oracle_sanitize.c"),
+          os.path.join(ROOT, "oracle", "zig_oracle.c"), "-o", exe, "-lquadmath", "-lm", "-lpthread"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+    out = _run([exe], env=env, timeout=600)
+    assert out.strip().endswith("ok"), out[-4000:]
+    assert "runtime error" not in out
