@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # bytes of a 1 GiB device copy to what the same counter read for it; the
 # commands and raw readings are in profiles/fill_kernel_counters.txt.
 # Reset to None whenever the fill kernel changes until it is re-measured.
-TRAFFIC = 8594787680
+TRAFFIC = 8595661457  # HBM bytes per launch of fill_kernel<normal, FP64, 256, 8> (FETCH_SIZE + WRITE_SIZE, scaled)
 N_C3 = 1 << 30
 N_C2 = 1 << 28
 
@@ -258,6 +258,27 @@ def serve_bench(torch, zig, seconds):
     return out
 
 
+def autotune_report(zig):
+    """Runs the autotuner on this device (cache in a temporary file) and
+    reports, per (dist, dtype, size class), the chosen shape and its time
+    against the built-in shape; the built-in table is restored after."""
+    import tempfile
+    d = tempfile.mkdtemp()
+    path = os.path.join(d, "tune.json")
+    t0 = time.perf_counter()
+    zig.zig_autotune(path, zig.TUNE_FORCE)
+    secs = time.perf_counter() - t0
+    with open(path) as f:
+        c = json.load(f)
+    os.remove(path)
+    os.rmdir(d)
+    zig.zig_autotune_reset()
+    rows = [{"dist": ["exp", "normal"][e["dist"]], "dtype": ["f64", "f32"][e["dtype"]], "n": e["n"],
+             "shape": "%dx%d/%d" % (e["wg"], e["spl"], e["step_blocks"]), "us": e["us"],
+             "builtin_us": e["default_us"]} for e in c["fill"]]
+    return {"seconds": round(secs, 2), "fill": rows, "batch": c["batch"]}
+
+
 def cpu_baseline(seconds_hint=True):
     from oracle import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
@@ -379,6 +400,9 @@ def main():
         log("batch: %s" % json.dumps(result["batch"]))
         if args.serve_seconds > 0:
             result["serving"] = serve_bench(torch, zig, args.serve_seconds)
+        log("autotuner")
+        result["autotune"] = autotune_report(zig)
+        log("autotune: %s" % json.dumps(result["autotune"]))
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -178,6 +178,39 @@ int zig_fill_batch_ex(const zig_request* reqs, uint32_t count, void* stream, con
  * Stops at the first failing request. */
 int zig_fill_each(const zig_request* reqs, uint32_t count, void* stream);
 
+/* Autotuner.  Times, on the current device, every compiled fill shape
+ * (workgroup size x Philox blocks per lane, and for fills above 2^21
+ * outputs the step of the work counter: 8K, 16K or 32K blocks) for each
+ * distribution, output type and size class (n <= 2^17, <= 2^21, <= 2^25,
+ * larger; timed at 2^16, 2^20, 2^24 and 2^28 outputs), and the batch
+ * kernel's shapes on a fixed mix of 1024 requests; fills and batches on
+ * that device then use the fastest (a candidate must beat the current
+ * choice by 1 %).  Outputs never depend on the shape, only the speed does.
+ * cache_path names a JSON file to load from and save to; NULL takes the
+ * environment variable ZIG_AUTOTUNE_CACHE, or none.  A cache is used only
+ * if it was written for the same architecture name and compute-unit count.
+ * Flags: ZIG_TUNE_LOAD loads only (ZIG_ESTATE if no matching cache exists);
+ * ZIG_TUNE_FORCE measures even if a matching cache exists.  Without any
+ * call, the first fill on a device loads ZIG_AUTOTUNE_CACHE if it names a
+ * matching file, else the built-in table (measured on MI355X) is used.
+ * Measuring takes a few seconds and 2 GiB of device memory; other work on
+ * the device meanwhile disturbs the timings, not the results.
+ * Errors: ZIG_EINVAL (flags, unwritable path), ZIG_ESTATE, ZIG_EHIP,
+ * ZIG_ENOMEM. */
+#define ZIG_TUNE_LOAD 1u
+#define ZIG_TUNE_FORCE 2u
+int zig_autotune(const char* cache_path, uint32_t flags);
+
+/* The shape a fill of (dist, dtype, n) uses on the current device; the
+ * counter step in Philox blocks goes to *step_blocks (may be NULL). */
+int zig_tuned_shape(uint32_t dist, uint32_t dtype, uint64_t n, zig_launch* out, uint32_t* step_blocks);
+
+/* The batch-kernel shape zig_fill_batch uses when none is given. */
+int zig_tuned_batch_shape(zig_batch_opts* out);
+
+/* Drops the current device's tuned table (back to the built-in one). */
+int zig_autotune_reset(void);
+
 /* ---------------------------------------------------------------------
  * Serving loop: continuous batching of fill requests from many clients.
  *

@@ -153,7 +153,7 @@ int check_params(uint32_t dist, double p0, double p1, double* scale, double* shi
 
 int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0, double p1,
               void* out, void* stream, const zig_launch* launch, bool trace, uint32_t* t_layer, int32_t* t_region,
-              uint32_t* t_words, uint32_t* t_tests) {
+              uint32_t* t_words, uint32_t* t_tests, const Shape* forced) {
   g_error.clear();
   if (dist != kDistExp && dist != kDistNormal) return fail(ZIG_EINVAL, "unknown distribution");
   if (dtype != kF64 && dtype != kF32) return fail(ZIG_EINVAL, "unknown dtype");
@@ -170,7 +170,7 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   if (((uintptr_t)out) % esize != 0) return fail(ZIG_EINVAL, "out is not aligned to its element size");
   if (n - 1 > UINT64_MAX - first) return fail(ZIG_EINVAL, "first_index + n exceeds 2^64");
 
-  Shape sh = tuned_shape(dist, dtype, n);
+  Shape sh = forced ? *forced : tuned_shape(dist, dtype, n);
   if (cfg.wg) sh.wg = cfg.wg;
   if (cfg.spl) sh.spl = cfg.spl;
   if (cfg.wg || cfg.spl) sh.chunk = 16384 / (sh.wg * sh.spl) ? 16384 / (sh.wg * sh.spl) : 1;
@@ -239,6 +239,11 @@ int device_tables_for(uint32_t i_max, const DevTable** out) { return device_tabl
 int params_for(uint32_t dist, double p0, double p1, double* scale, double* shift) {
   return check_params(dist, p0, p1, scale, shift);
 }
+int fill_shaped(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0, double p1,
+                void* out, void* stream, const Shape& shape) {
+  return fill_impl(dist, dtype, seed, first, n, p0, p1, out, stream, nullptr, false, nullptr, nullptr, nullptr,
+                   nullptr, &shape);
+}
 void set_error(const std::string& msg) { g_error = msg; }
 void clear_error() { g_error.clear(); }
 
@@ -285,26 +290,26 @@ int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out) {
 int zig_fill(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
              void* out, void* stream, const zig_launch* launch) {
   return zig::fill_impl(dist, dtype, seed, first_index, n, p0, p1, out, stream, launch, false, nullptr, nullptr,
-                        nullptr, nullptr);
+                        nullptr, nullptr, nullptr);
 }
 
 int zig_fill_exp(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dtype, double lambda, void* out,
                  void* stream) {
   return zig::fill_impl(ZIG_EXP, dtype, seed, first_index, n, lambda, 0.0, out, stream, nullptr, false, nullptr,
-                        nullptr, nullptr, nullptr);
+                        nullptr, nullptr, nullptr, nullptr);
 }
 
 int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dtype, double mu, double sigma,
                     void* out, void* stream) {
   return zig::fill_impl(ZIG_NORMAL, dtype, seed, first_index, n, mu, sigma, out, stream, nullptr, false, nullptr,
-                        nullptr, nullptr, nullptr);
+                        nullptr, nullptr, nullptr, nullptr);
 }
 
 int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0,
                    double p1, void* out, uint32_t* layer, int32_t* region, uint32_t* words, uint32_t* tests,
                    void* stream, const zig_launch* launch) {
   return zig::fill_impl(dist, dtype, seed, first_index, n, p0, p1, out, stream, launch, true, layer, region, words,
-                        tests);
+                        tests, nullptr);
 }
 
 const char* zig_last_error(void) { return zig::g_error.c_str(); }

@@ -20,6 +20,7 @@
 
 #include "../../include/zig.h"
 #include "zig_internal.hpp"
+#include "zig_tune.hpp"
 
 namespace zig {
 namespace {
@@ -151,7 +152,8 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   clear_error();
   if (count > 0 && reqs == nullptr) return fail(ZIG_EINVAL, "reqs is null");
   if (count > kMaxBatch) return fail(ZIG_EINVAL, "more than 2^20 requests in one batch");
-  uint32_t wg = 256, spl = 4, flags = 0;
+  uint32_t wg = 0, spl = 0, flags = 0;
+  tuned_batch_shape(&wg, &spl);
   if (opts) {
     if (opts->wg) wg = opts->wg;
     if (opts->spl) spl = opts->spl;

@@ -38,6 +38,7 @@
 
 #include "../../include/zig.h"
 #include "zig_internal.hpp"
+#include "zig_tune.hpp"
 
 namespace zig {
 namespace {
@@ -516,6 +517,7 @@ int setup_device(Server* s) {
   ZIG_CK(hipGetDevice(&s->dev_id), "hipGetDevice");
   const int r = device_tables_for(256, &s->tabs);
   if (r != ZIG_OK) return r;
+  tuned_batch_shape(&s->wg, &s->spl);
   ZIG_CK((hipError_t)batch_groups(s->wg, s->spl, &s->groups), "batch occupancy");
   if (s->cfg.arena) {
     s->arena_dev = static_cast<char*>(s->cfg.arena);

@@ -1,7 +1,345 @@
-// Launch-shape table of the fill kernels.
+// Launch-shape table and autotuner.
+//
+// The tuner times every compiled fill shape (workgroup size x Philox blocks
+// per lane, and for large fills the counter step) for each distribution,
+// output type and size class on the current device, plus the batch
+// kernel's shapes on a fixed mixed batch, and keeps the fastest per device.
+// Outputs never depend on the shape; only the speed does.  Results can be
+// saved to and loaded from a small JSON file keyed by the device's
+// architecture name and compute-unit count.
 #include "zig_tune.hpp"
 
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/zig.h"
+#include "zig_internal.hpp"
+
 namespace zig {
+namespace {
+
+struct Entry {
+  Shape shape;
+  double us = 0.0;          // measured time of the chosen shape
+  double default_us = 0.0;  // measured time of the built-in shape
+};
+
+struct Table {
+  Entry fill[2][2][kSizeClasses];  // [dist][dtype][class]
+  uint32_t batch_wg = 0, batch_spl = 0;
+  double batch_us = 0.0, batch_default_us = 0.0;
+};
+
+struct DeviceTune {
+  bool autoload_tried = false;
+  bool valid = false;
+  Table table;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceTune> g_dev;
+
+const uint64_t kClassN[kSizeClasses] = {1ull << 16, 1ull << 20, 1ull << 24, 1ull << 28};
+
+uint32_t chunk_for(uint32_t wg, uint32_t spl, uint32_t step_blocks) {
+  const uint32_t c = step_blocks / (wg * spl);
+  return c ? c : 1;
+}
+
+// Built-in table: the autotuner's choices on MI355X (256 CUs), as
+// {wg, spl, counter step in blocks} per [dist][dtype][size class].
+const uint32_t kBuiltin[2][2][kSizeClasses][3] = {
+    {{{512, 2, 16384}, {512, 4, 16384}, {512, 4, 32768}, {512, 4, 8192}},     // exp FP64
+     {{512, 1, 16384}, {1024, 2, 16384}, {1024, 2, 8192}, {512, 4, 16384}}},  // exp FP32
+    {{{512, 1, 16384}, {1024, 2, 16384}, {256, 8, 16384}, {256, 8, 8192}},    // normal FP64
+     {{256, 1, 16384}, {512, 4, 16384}, {512, 4, 16384}, {128, 8, 8192}}},    // normal FP32
+};
+const uint32_t kBuiltinBatch[2] = {128, 8};
+
+Shape builtin_shape(uint32_t dist, uint32_t dtype, uint32_t cls) {
+  const uint32_t* e = kBuiltin[dist & 1][dtype & 1][cls < kSizeClasses ? cls : kSizeClasses - 1];
+  Shape s;
+  s.wg = e[0];
+  s.spl = e[1];
+  s.chunk = chunk_for(s.wg, s.spl, e[2]);
+  return s;
+}
+
+int fail(int code, const std::string& m) {
+  set_error(m);
+  return code;
+}
+
+int device_key(int* dev, std::string* arch, int* cus) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (arch || cus) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, *dev);
+    if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+    if (arch) *arch = p.gcnArchName;
+    if (cus) *cus = p.multiProcessorCount;
+  }
+  return ZIG_OK;
+}
+
+std::string to_json(const Table& t, const std::string& arch, int cus) {
+  std::ostringstream o;
+  char line[512];
+  o << "{\n  \"format\": \"zig-autotune-1\",\n  \"arch\": \"" << arch << "\",\n  \"cus\": " << cus
+    << ",\n  \"fill\": [\n";
+  bool first = true;
+  for (uint32_t d = 0; d < 2; ++d)
+    for (uint32_t dt = 0; dt < 2; ++dt)
+      for (uint32_t c = 0; c < kSizeClasses; ++c) {
+        const Entry& e = t.fill[d][dt][c];
+        std::snprintf(line, sizeof(line),
+                      "%s    {\"dist\": %u, \"dtype\": %u, \"class\": %u, \"n\": %llu, \"wg\": %u, \"spl\": %u, "
+                      "\"step_blocks\": %u, \"us\": %.3f, \"default_us\": %.3f}",
+                      first ? "" : ",\n", d, dt, c, (unsigned long long)kClassN[c], e.shape.wg, e.shape.spl,
+                      e.shape.chunk * e.shape.wg * e.shape.spl, e.us, e.default_us);
+        o << line;
+        first = false;
+      }
+  std::snprintf(line, sizeof(line),
+                "\n  ],\n  \"batch\": {\"wg\": %u, \"spl\": %u, \"us\": %.3f, \"default_us\": %.3f}\n}\n", t.batch_wg,
+                t.batch_spl, t.batch_us, t.batch_default_us);
+  o << line;
+  return o.str();
+}
+
+// Reads a file written by to_json; false if it is not for this device or
+// does not parse.
+bool from_json(const std::string& text, const std::string& arch, int cus, Table* out, std::string* why) {
+  const std::string akey = "\"arch\": \"" + arch + "\"";
+  if (text.find("\"format\": \"zig-autotune-1\"") == std::string::npos) {
+    *why = "not an autotune cache";
+    return false;
+  }
+  if (text.find(akey) == std::string::npos || text.find("\"cus\": " + std::to_string(cus) + ",") == std::string::npos) {
+    *why = "cache written for another device";
+    return false;
+  }
+  Table t;
+  bool seen[2][2][kSizeClasses] = {};
+  std::istringstream in(text);
+  std::string line;
+  bool batch = false;
+  while (std::getline(in, line)) {
+    unsigned d, dt, c, wg, spl, step;
+    unsigned long long n;
+    double us, dus;
+    const char* p = std::strchr(line.c_str(), '{');
+    if (!p) continue;
+    if (std::sscanf(p,
+                    "{\"dist\": %u, \"dtype\": %u, \"class\": %u, \"n\": %llu, \"wg\": %u, \"spl\": %u, "
+                    "\"step_blocks\": %u, \"us\": %lf, \"default_us\": %lf}",
+                    &d, &dt, &c, &n, &wg, &spl, &step, &us, &dus) == 9) {
+      if (d > 1 || dt > 1 || c >= kSizeClasses || !shape_supported(wg, spl)) {
+        *why = "bad fill entry";
+        return false;
+      }
+      Entry& e = t.fill[d][dt][c];
+      e.shape.wg = wg;
+      e.shape.spl = spl;
+      e.shape.chunk = chunk_for(wg, spl, step);
+      e.us = us;
+      e.default_us = dus;
+      seen[d][dt][c] = true;
+      continue;
+    }
+    const char* b = std::strstr(line.c_str(), "\"batch\": {");
+    if (b && std::sscanf(b, "\"batch\": {\"wg\": %u, \"spl\": %u, \"us\": %lf, \"default_us\": %lf}", &wg, &spl, &us,
+                         &dus) == 4) {
+      if (!batch_shape_supported(wg, spl)) {
+        *why = "bad batch entry";
+        return false;
+      }
+      t.batch_wg = wg;
+      t.batch_spl = spl;
+      t.batch_us = us;
+      t.batch_default_us = dus;
+      batch = true;
+    }
+  }
+  for (uint32_t d = 0; d < 2; ++d)
+    for (uint32_t dt = 0; dt < 2; ++dt)
+      for (uint32_t c = 0; c < kSizeClasses; ++c)
+        if (!seen[d][dt][c]) {
+          *why = "incomplete cache";
+          return false;
+        }
+  if (!batch) {
+    *why = "cache has no batch entry";
+    return false;
+  }
+  *out = t;
+  return true;
+}
+
+bool load_file(const std::string& path, const std::string& arch, int cus, Table* out, std::string* why) {
+  std::ifstream f(path);
+  if (!f) {
+    *why = "cannot read " + path;
+    return false;
+  }
+  std::stringstream ss;
+  ss << f.rdbuf();
+  return from_json(ss.str(), arch, cus, out, why);
+}
+
+// Average time of one call of `launch` in microseconds: two warm-up calls,
+// then `reps` calls between events, best of two rounds.
+template <class F>
+int time_us(hipStream_t st, int reps, F launch, double* us) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return fail(ZIG_EHIP, "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(ZIG_EHIP, "hipEventCreate");
+  }
+  int r = ZIG_OK;
+  double best = 1e30;
+  for (int w = 0; w < 2 && r == ZIG_OK; ++w) r = launch();
+  for (int round = 0; round < 2 && r == ZIG_OK; ++round) {
+    (void)hipEventRecord(a, st);
+    for (int i = 0; i < reps && r == ZIG_OK; ++i) r = launch();
+    (void)hipEventRecord(b, st);
+    if (r == ZIG_OK && hipEventSynchronize(b) != hipSuccess) r = fail(ZIG_EHIP, "hipEventSynchronize");
+    float ms = 0.0f;
+    if (r == ZIG_OK && hipEventElapsedTime(&ms, a, b) != hipSuccess) r = fail(ZIG_EHIP, "hipEventElapsedTime");
+    if (r == ZIG_OK) best = std::min(best, 1e3 * (double)ms / reps);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *us = best;
+  return r;
+}
+
+uint64_t splitmix(uint64_t* s) {
+  uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int measure(Table* t) {
+  hipStream_t st = nullptr;
+  void* buf = nullptr;
+  const size_t bytes = kClassN[kSizeClasses - 1] * 8;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+  e = hipMalloc(&buf, bytes);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(st);
+    return fail(ZIG_ENOMEM, std::string("hipMalloc(autotune buffer): ") + hipGetErrorString(e));
+  }
+  int r = ZIG_OK;
+  const uint32_t wgs[] = {64, 128, 256, 512, 1024};
+  const uint32_t spls[] = {1, 2, 4, 8};
+  for (uint32_t d = 0; d < 2 && r == ZIG_OK; ++d)
+    for (uint32_t dt = 0; dt < 2 && r == ZIG_OK; ++dt)
+      for (uint32_t c = 0; c < kSizeClasses && r == ZIG_OK; ++c) {
+        const uint64_t n = kClassN[c];
+        const int reps = c <= 1 ? 40 : (c == 2 ? 10 : 3);
+        const double p0 = d == 0 ? 1.5 : 0.25, p1 = 2.0;
+        auto run = [&](const Shape& s) {
+          return fill_shaped(d, dt, 1234567 + c, 0, n, p0, p1, buf, st, s);
+        };
+        Entry best;
+        best.us = 1e30;
+        const Shape def = builtin_shape(d, dt, c);
+        r = time_us(st, reps, [&] { return run(def); }, &best.default_us);
+        best.shape = def;
+        best.us = best.default_us;
+        std::vector<uint32_t> steps = {16384};
+        if (c >= 2) steps = {8192, 16384, 32768};
+        for (uint32_t wg : wgs)
+          for (uint32_t spl : spls) {
+            if (!shape_supported(wg, spl)) continue;
+            for (uint32_t step : steps) {
+              if (r != ZIG_OK) break;
+              Shape s;
+              s.wg = wg;
+              s.spl = spl;
+              s.chunk = chunk_for(wg, spl, step);
+              double us = 0.0;
+              r = time_us(st, reps, [&] { return run(s); }, &us);
+              // a challenger must beat the current choice by 1 % to count
+              if (r == ZIG_OK && us < best.us * 0.99) {
+                best.us = us;
+                best.shape = s;
+              }
+            }
+          }
+        t->fill[d][dt][c] = best;
+      }
+  // batch kernel: a fixed mix of 1024 requests, sizes floor(2^(20 U)),
+  // both distributions and dtypes, outputs 16-byte aligned in `buf`
+  if (r == ZIG_OK) {
+    std::vector<zig_request> reqs(1024);
+    uint64_t rs = 42, off = 0;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+      const double u = (double)(splitmix(&rs) >> 11) * 0x1.0p-53;
+      uint64_t n = (uint64_t)std::floor(std::exp2(20.0 * u));
+      if (off + n * 8 > bytes) n = 0;  // stays inside the buffer (an empty request is skipped)
+      zig_request& q = reqs[i];
+      q.dist = (uint32_t)(i & 1);
+      q.dtype = (uint32_t)((i >> 1) & 1);
+      q.seed = i;
+      q.first_index = 0;
+      q.n = n;
+      q.p0 = q.dist == 0 ? 2.0 : 0.5;
+      q.p1 = 1.5;
+      q.out = static_cast<char*>(buf) + off;
+      off += (n * 8 + 15) & ~(uint64_t)15;
+    }
+    const uint32_t shapes[][2] = {{64, 4}, {128, 4}, {128, 8}, {256, 2}, {256, 4}, {512, 2}};
+    double best_us = 1e30, def_us = 0.0;
+    uint32_t bw = kBuiltinBatch[0], bs = kBuiltinBatch[1];
+    for (const auto& sh : shapes) {
+      zig_batch_opts o;
+      o.wg = sh[0];
+      o.spl = sh[1];
+      o.flags = 0;
+      double us = 0.0;
+      r = time_us(st, 5, [&] { return zig_fill_batch_ex(reqs.data(), (uint32_t)reqs.size(), st, &o); }, &us);
+      if (r != ZIG_OK) break;
+      if (sh[0] == kBuiltinBatch[0] && sh[1] == kBuiltinBatch[1]) def_us = us;
+      if (us < best_us) {
+        best_us = us;
+        bw = sh[0];
+        bs = sh[1];
+      }
+    }
+    if (r == ZIG_OK && best_us > def_us * 0.99) {  // keep the default unless clearly faster
+      best_us = def_us;
+      bw = kBuiltinBatch[0];
+      bs = kBuiltinBatch[1];
+    }
+    t->batch_wg = bw;
+    t->batch_spl = bs;
+    t->batch_us = best_us;
+    t->batch_default_us = def_us;
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(buf);
+  (void)hipStreamDestroy(st);
+  return r;
+}
+
+}  // namespace
 
 bool shape_supported(uint32_t wg, uint32_t spl) {
   const bool w = wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024;
@@ -9,24 +347,131 @@ bool shape_supported(uint32_t wg, uint32_t spl) {
   return w && s && wg * spl <= 2048;
 }
 
-Shape tuned_shape(uint32_t dist, uint32_t dtype, uint64_t n) {
-  (void)n;
-  Shape s;
-  // measured on MI355X at 2^30 outputs: the exponential prefers wide
-  // workgroups, the normal distribution (heavier slow path, more
-  // registers) longer tiles on narrower ones
-  if (dist == 0) {
-    s.wg = 512;
-    s.spl = 4;
-  } else {
-    s.wg = 128;
-    s.spl = 8;
+uint32_t size_class(uint64_t n) {
+  if (n <= (1ull << 17)) return 0;
+  if (n <= (1ull << 21)) return 1;
+  if (n <= (1ull << 25)) return 2;
+  return 3;
+}
+
+// tuned entry of the current device, loading ZIG_AUTOTUNE_CACHE on first use
+static const Table* device_table() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceTune& t = g_dev[dev];
+  if (!t.autoload_tried) {
+    t.autoload_tried = true;
+    const char* env = std::getenv("ZIG_AUTOTUNE_CACHE");
+    if (env && *env) {
+      hipDeviceProp_t p;
+      std::string why;
+      if (hipGetDeviceProperties(&p, dev) == hipSuccess && load_file(env, p.gcnArchName, p.multiProcessorCount,
+                                                                     &t.table, &why))
+        t.valid = true;
+    }
   }
-  (void)dtype;
-  // about 16K blocks per step of the tile counter
-  s.chunk = 16384 / (s.wg * s.spl);
-  if (s.chunk < 1) s.chunk = 1;
-  return s;
+  return t.valid ? &t.table : nullptr;
+}
+
+Shape tuned_shape(uint32_t dist, uint32_t dtype, uint64_t n) {
+  const uint32_t c = size_class(n);
+  const Table* t = device_table();
+  if (t && dist < 2 && dtype < 2) return t->fill[dist][dtype][c].shape;
+  return builtin_shape(dist, dtype, c);
+}
+
+void tuned_batch_shape(uint32_t* wg, uint32_t* spl) {
+  const Table* t = device_table();
+  *wg = t ? t->batch_wg : kBuiltinBatch[0];
+  *spl = t ? t->batch_spl : kBuiltinBatch[1];
 }
 
 }  // namespace zig
+
+extern "C" {
+
+int zig_autotune(const char* cache_path, uint32_t flags) {
+  zig::clear_error();
+  if (flags & ~(uint32_t)(ZIG_TUNE_LOAD | ZIG_TUNE_FORCE)) return zig::fail(ZIG_EINVAL, "unknown flags");
+  if ((flags & ZIG_TUNE_LOAD) && (flags & ZIG_TUNE_FORCE))
+    return zig::fail(ZIG_EINVAL, "ZIG_TUNE_LOAD and ZIG_TUNE_FORCE exclude each other");
+  std::string path;
+  if (cache_path) {
+    path = cache_path;
+  } else if (const char* env = std::getenv("ZIG_AUTOTUNE_CACHE")) {
+    path = env;
+  }
+  int dev = 0, cus = 0;
+  std::string arch;
+  int r = zig::device_key(&dev, &arch, &cus);
+  if (r != ZIG_OK) return r;
+  zig::Table t;
+  std::string why;
+  if (!(flags & ZIG_TUNE_FORCE) && !path.empty() && zig::load_file(path, arch, cus, &t, &why)) {
+    std::lock_guard<std::mutex> lk(zig::g_mu);
+    zig::DeviceTune& d = zig::g_dev[dev];
+    d.autoload_tried = true;
+    d.valid = true;
+    d.table = t;
+    return ZIG_OK;
+  }
+  if (flags & ZIG_TUNE_LOAD)
+    return zig::fail(ZIG_ESTATE, path.empty() ? std::string("no cache path") : "cache not used: " + why);
+  const zig::DevTable* tabs = nullptr;
+  r = zig::device_tables_for(256, &tabs);
+  if (r != ZIG_OK) return r;
+  r = zig::measure(&t);
+  if (r != ZIG_OK) return r;
+  {
+    std::lock_guard<std::mutex> lk(zig::g_mu);
+    zig::DeviceTune& d = zig::g_dev[dev];
+    d.autoload_tried = true;
+    d.valid = true;
+    d.table = t;
+  }
+  if (!path.empty()) {
+    const std::string tmp = path + ".tmp";
+    {
+      std::ofstream f(tmp);
+      f << zig::to_json(t, arch, cus);
+      if (!f) return zig::fail(ZIG_EINVAL, "cannot write " + tmp);
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0) return zig::fail(ZIG_EINVAL, "cannot write " + path);
+  }
+  return ZIG_OK;
+}
+
+int zig_tuned_shape(uint32_t dist, uint32_t dtype, uint64_t n, zig_launch* out, uint32_t* step_blocks) {
+  zig::clear_error();
+  if (!out) return zig::fail(ZIG_EINVAL, "out is null");
+  if (dist > 1 || dtype > 1) return zig::fail(ZIG_EINVAL, "unknown distribution or dtype");
+  const zig::Shape s = zig::tuned_shape(dist, dtype, n);
+  out->i_max = 256;
+  out->wg = s.wg;
+  out->spl = s.spl;
+  if (step_blocks) *step_blocks = s.chunk * s.wg * s.spl;
+  return ZIG_OK;
+}
+
+int zig_tuned_batch_shape(zig_batch_opts* out) {
+  zig::clear_error();
+  if (!out) return zig::fail(ZIG_EINVAL, "out is null");
+  zig::tuned_batch_shape(&out->wg, &out->spl);
+  out->flags = 0;
+  return ZIG_OK;
+}
+
+int zig_autotune_reset(void) {
+  zig::clear_error();
+  int dev = 0;
+  const int r = zig::device_key(&dev, nullptr, nullptr);
+  if (r != ZIG_OK) return r;
+  std::lock_guard<std::mutex> lk(zig::g_mu);
+  zig::DeviceTune& d = zig::g_dev[dev];
+  d.autoload_tried = true;  // the environment's cache is not reloaded either
+  d.valid = false;
+  return ZIG_OK;
+}
+
+}  // extern "C"

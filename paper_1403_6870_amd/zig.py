@@ -118,6 +118,11 @@ _fill_trace = _sig("zig_fill_trace", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp
 _fill_batch = _sig("zig_fill_batch", i32, [ctypes.POINTER(Request), u32, vp])
 _fill_batch_ex = _sig("zig_fill_batch_ex", i32, [ctypes.POINTER(Request), u32, vp, ctypes.POINTER(BatchOpts)])
 _fill_each = _sig("zig_fill_each", i32, [ctypes.POINTER(Request), u32, vp])
+_autotune = _sig("zig_autotune", i32, [ctypes.c_char_p, u32])
+_tuned_shape = _sig("zig_tuned_shape", i32, [u32, u32, u64, ctypes.POINTER(Launch), ctypes.POINTER(u32)])
+_tuned_batch_shape = _sig("zig_tuned_batch_shape", i32, [ctypes.POINTER(BatchOpts)])
+_autotune_reset = _sig("zig_autotune_reset", i32, [])
+TUNE_LOAD, TUNE_FORCE = 1, 2
 _srv_p = ctypes.c_void_p
 _server_now = _sig("zig_server_now_ns", u64, [])
 _server_create = _sig("zig_server_create", i32, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_srv_p)])
@@ -134,7 +139,8 @@ _last_error = _sig("zig_last_error", ctypes.c_char_p, [])
 _version = _sig("zig_version", ctypes.c_char_p, [])
 
 EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
-           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_server_now_ns", "zig_server_create",
+           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_autotune", "zig_tuned_shape",
+           "zig_tuned_batch_shape", "zig_autotune_reset", "zig_server_now_ns", "zig_server_create",
            "zig_server_submit", "zig_server_wait", "zig_server_release", "zig_server_drop_client",
            "zig_server_counters", "zig_server_set_counters", "zig_server_stats_get", "zig_server_replay",
            "zig_server_destroy", "zig_last_error", "zig_version"]
@@ -214,6 +220,27 @@ def zig_fill_each(reqs, stream_ptr=None):
     if not isinstance(reqs, ctypes.Array):
         reqs = (Request * len(reqs))(*reqs)
     _check(_fill_each(reqs, len(reqs), stream_ptr))
+
+
+def zig_autotune(cache_path=None, flags=0):
+    _check(_autotune(cache_path.encode() if cache_path else None, flags))
+
+
+def zig_tuned_shape(dist, dtype, n):
+    """(wg, spl, step_blocks) a fill of (dist, dtype, n) uses."""
+    la, step = Launch(), u32()
+    _check(_tuned_shape(dist, dtype, n, ctypes.byref(la), ctypes.byref(step)))
+    return la.wg, la.spl, step.value
+
+
+def zig_tuned_batch_shape():
+    o = BatchOpts()
+    _check(_tuned_batch_shape(ctypes.byref(o)))
+    return o.wg, o.spl
+
+
+def zig_autotune_reset():
+    _check(_autotune_reset())
 
 
 def zig_server_now_ns():

@@ -93,3 +93,11 @@ def test_fill_argument_validation(zig):
     zig.zig_fill_exp(1, 0, 0, 0, 1.0, None)
     zig.zig_fill_normal(1, 2 ** 64 - 1, 0, 1, 0.0, 1.0, None)
     assert zig.zig_last_error() == ""
+
+
+def test_autotune_bad_flags_refused_before_device_work():
+    from paper_1403_6870_amd import zig
+    for flags in (4, 3):
+        with pytest.raises(zig.ZigError) as e:
+            zig.zig_autotune(None, flags)
+        assert e.value.status == zig.ZIG_EINVAL
