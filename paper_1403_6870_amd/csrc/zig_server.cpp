@@ -56,6 +56,15 @@ int fail(int code, const std::string& m) {
   return code;
 }
 
+// Deadline `ns` from now for timed condition waits.  On the system clock,
+// whose waits are plain pthread_cond_timedwait calls (a steady-clock wait
+// goes through pthread_cond_clockwait, which some thread checkers do not
+// follow).
+std::chrono::system_clock::time_point wall_deadline(uint64_t ns) {
+  return std::chrono::system_clock::now() +
+         std::chrono::duration_cast<std::chrono::system_clock::duration>(std::chrono::nanoseconds(ns));
+}
+
 // First-fit allocator over the output arena in 256-byte granules.
 class Arena {
  public:
@@ -338,7 +347,7 @@ void sched_loop(Server* s) {
       while (!s->stop.load() && !s->intake.empty() && s->intake.size() < s->cfg.max_batch) {
         const uint64_t t = now_ns();
         if (t >= deadline) break;
-        s->cv_sched.wait_for(lk, std::chrono::nanoseconds(deadline - t));
+        s->cv_sched.wait_until(lk, wall_deadline(deadline - t));
       }
       if (s->stop.load()) break;
       if (s->intake.empty() || !free_slot(s, &k, &j)) continue;
@@ -677,7 +686,7 @@ int zig_server_wait(zig_server* srv, uint64_t ticket, int64_t timeout_us, zig_co
   };
   if (timeout_us < 0) {
     s->cv_done.wait(lk, ready);
-  } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+  } else if (!s->cv_done.wait_until(lk, zig::wall_deadline((uint64_t)timeout_us * 1000), ready)) {
     return zig::fail(ZIG_EBUSY, "timed out");
   }
   auto it = s->tickets.find(ticket);
