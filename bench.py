@@ -258,6 +258,36 @@ def serve_bench(torch, zig, seconds):
     return out
 
 
+def moments_bench(torch, zig):
+    """Fused generate-and-reduce (raw moment sums, no output written): the
+    rate at 2^32 FP64 draws per distribution, and Appendix B's table of the
+    raw moments X1..X5 from 10^12 draws of Exp(1) and N(0, 1) against the
+    closed forms 1, 2, 6, 24, 120 and 0, 1, 0, 3, 0."""
+    out = {}
+    st = torch.cuda.current_stream()
+    for name, dist, p0, p1 in [("exp", 0, 2.5, 0.0), ("normal", 1, -1.0, 3.0)]:
+        n = 1 << 32
+        zig.moments(dist, 0, 1 << 24, 3, 0, p0, p1)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        zig.moments(dist, 0, n, 3, 0, p0, p1)
+        b.record(st)
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        out[name + "_2^32_f64"] = {"Gsamples/s": round(n / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 3)}
+    appb = {}
+    for name, dist, want in [("exp", 0, [1, 2, 6, 24, 120]), ("normal", 1, [0, 1, 0, 3, 0])]:
+        n = 10 ** 12
+        t0 = time.perf_counter()
+        s = zig.moments(dist, 0, n, 2014, 0, 1.0, 1.0).cpu().numpy()
+        secs = time.perf_counter() - t0
+        appb[name] = {"draws": n, "seconds": round(secs, 2), "moments": [float(v / n) for v in s],
+                      "closed_form": want}
+    out["appendix_b_1e12"] = appb
+    return out
+
+
 def autotune_report(zig):
     """Runs the autotuner on this device (cache in a temporary file) and
     reports, per (dist, dtype, size class), the chosen shape and its time
@@ -400,6 +430,9 @@ def main():
         log("batch: %s" % json.dumps(result["batch"]))
         if args.serve_seconds > 0:
             result["serving"] = serve_bench(torch, zig, args.serve_seconds)
+        log("fused generate-and-reduce")
+        result["moments"] = moments_bench(torch, zig)
+        log("moments: %s" % json.dumps(result["moments"]))
         log("autotuner")
         result["autotune"] = autotune_report(zig)
         log("autotune: %s" % json.dumps(result["autotune"]))

@@ -143,6 +143,26 @@ int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
                    double p1, void* out, uint32_t* layer, int32_t* region, uint32_t* words, uint32_t* tests,
                    void* stream, const zig_launch* launch);
 
+/* Fused generate-and-reduce: the raw moment sums S_p = sum over k of x_k^p,
+ * p = 1..5, of the n outputs x_k that zig_fill with the same arguments
+ * would write (as written: doubles, or floats widened to double; powers
+ * formed as x*x, x^2*x, x^2*x^2, x^4*x), written to sums[0..4] in device
+ * memory (caller-owned, 8-byte aligned); no output is written to HBM.  This
+ * is the generate-and-aggregate form of the paper's benchmark (section 3)
+ * and of Appendix B's raw-moment test.  The additions follow one fixed
+ * order, so the result is the same bits on every run and device: tiles of
+ * 2048 Philox blocks from the first block (first_index / 2 for FP64, / 4
+ * for FP32); in a tile, lane l = 0..255 adds, from +0, the outputs of
+ * blocks l, l + 256, ..., l + 1792 in order; the 256 lane sums are reduced
+ * by halving (v[l] += v[l + s] for s = 128, 64, ..., 1); groups of 256
+ * tiles likewise (the last one padded with +0); the total is +0 plus the
+ * group sums in order.  launch may be NULL; only launch->i_max is honoured
+ * (wg and spl must be 0 or 256 and 8).  Asynchronous on `stream`; uses
+ * 2.6 MB of device scratch per stream, kept until the process ends.
+ * Errors: as zig_fill (sums in place of out). */
+int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
+                double* sums, void* stream, const zig_launch* launch);
+
 /* One request of a batch: dist ZIG_EXP (p0 = lambda) or ZIG_NORMAL (p0 = mu,
  * p1 = sigma), dtype, seed, first_index, n and a caller-owned device output
  * of n elements; the same contract as zig_fill for each request. */

@@ -40,9 +40,12 @@ class Tables(ctypes.Structure):
         ("W", ctypes.c_double * (MAXI + 1)), ("H", ctypes.c_double * (MAXI + 1)),
         ("q", ctypes.c_uint64 * (MAXI + 1)), ("T", ctypes.c_uint64 * MAXI), ("A", ctypes.c_uint32 * MAXI),
         ("eps", ctypes.c_double), ("K_eps", ctypes.c_uint64), ("X0", ctypes.c_double), ("invX0", ctypes.c_double),
+        ("eps_cvx", ctypes.c_double), ("del_ccv", ctypes.c_double), ("K_cvx", ctypes.c_uint64),
+        ("K_ccv", ctypes.c_uint64), ("accel", ctypes.c_int),
         ("hpX", (ctypes.c_char * 48) * (MAXI + 1)), ("hpf", (ctypes.c_char * 48) * (MAXI + 1)),
         ("hpA", (ctypes.c_char * 48) * (MAXI + 1)),
         ("hp_area", ctypes.c_char * 48), ("hp_total", ctypes.c_char * 48), ("hp_eps", ctypes.c_char * 48),
+        ("hp_eps_cvx", ctypes.c_char * 48), ("hp_del_ccv", ctypes.c_char * 48),
     ]
 
 
@@ -73,6 +76,8 @@ def lib():
         L.orc_sample_region.restype = i32
         L.orc_alias_draw.argtypes = [tp, u64]
         L.orc_alias_draw.restype = u32
+        L.orc_moments.argtypes = [i32, i32, tp, tp, u64, u64, u64, dbl, dbl, ctypes.POINTER(dbl), i32]
+        L.orc_moments.restype = i32
         L.orc_tables_size.argtypes = []
         L.orc_tables_size.restype = u64
         if L.orc_tables_size() != ctypes.sizeof(Tables):
@@ -89,12 +94,15 @@ def philox(ctr, key):
     return [int(v) for v in o]
 
 
-def tables(dist, i_max=256):
-    key = (dist, i_max)
+def tables(dist, i_max=256, accel=False):
+    """Tables of `dist`; accel=True gives the normal tables that select the
+    accelerated overhang variant."""
+    key = (dist, i_max, bool(accel) and dist == NORMAL)
     if key not in _tables:
         t = Tables()
         if lib().orc_build_tables(dist, i_max, ctypes.byref(t)) != 0:
             raise ValueError("unsupported table %r" % (key,))
+        t.accel = 1 if key[2] else 0
         _tables[key] = t
     return _tables[key]
 
@@ -116,18 +124,20 @@ def table_arrays(dist, i_max=256):
         "hpA": [t.hpA[k].value.decode() for k in range(L + 1)],
         "hp_area": t.hp_area.decode(), "hp_total": t.hp_total.decode(),
         "hp_eps": t.hp_eps.decode(),
+        "eps_cvx": t.eps_cvx, "del_ccv": t.del_ccv, "K_cvx": int(t.K_cvx), "K_ccv": int(t.K_ccv),
+        "hp_eps_cvx": t.hp_eps_cvx.decode(), "hp_del_ccv": t.hp_del_ccv.decode(),
     }
 
 
-def _tabs(dist, i_max):
+def _tabs(dist, i_max, accel=False):
     ex = tables(EXP, i_max)
-    nt = tables(NORMAL, i_max) if dist == NORMAL else None
+    nt = tables(NORMAL, i_max, accel) if dist == NORMAL else None
     return ctypes.byref(ex), (ctypes.byref(nt) if nt is not None else None)
 
 
-def fill(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256):
+def fill(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256, accel=False):
     out = np.empty(n, dtype=np.float64 if dtype == F64 else np.float32)
-    ex, nt = _tabs(dist, i_max)
+    ex, nt = _tabs(dist, i_max, accel)
     r = lib().orc_fill(dist, dtype, ex, nt, seed, first, n, scale, shift,
                        out.ctypes.data if n else None, threads)
     if r != 0:
@@ -135,13 +145,23 @@ def fill(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256):
     return out
 
 
-def fill_trace(dist, dtype, seed, first, n, scale, shift=0.0, i_max=256):
+def moments(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256, accel=False):
+    """Raw moment sums (S1..S5) of the outputs of the same fill, in the
+    fixed summation order of orc_moments."""
+    out = (ctypes.c_double * 5)()
+    ex, nt = _tabs(dist, i_max, accel)
+    if lib().orc_moments(dist, dtype, ex, nt, seed, first, n, scale, shift, out, threads) != 0:
+        raise ValueError("orc_moments rejected its arguments")
+    return np.array(list(out))
+
+
+def fill_trace(dist, dtype, seed, first, n, scale, shift=0.0, i_max=256, accel=False):
     out = np.empty(n, dtype=np.float64 if dtype == F64 else np.float32)
     layer = np.empty(n, dtype=np.uint32)
     region = np.empty(n, dtype=np.int32)
     words = np.empty(n, dtype=np.uint32)
     tests = np.empty(n, dtype=np.uint32)
-    ex, nt = _tabs(dist, i_max)
+    ex, nt = _tabs(dist, i_max, accel)
     r = lib().orc_fill_trace(dist, dtype, ex, nt, seed, first, n, scale, shift,
                              out.ctypes.data, layer.ctypes.data, region.ctypes.data,
                              words.ctypes.data, tests.ctypes.data)
@@ -150,27 +170,28 @@ def fill_trace(dist, dtype, seed, first, n, scale, shift=0.0, i_max=256):
     return out, layer, region, words, tests
 
 
-def box_attempt(dist, i_max, j, k1, k2):
+def box_attempt(dist, i_max, j, k1, k2, accel=False):
     x = ctypes.c_double()
-    r = lib().orc_box_attempt(ctypes.byref(tables(dist, i_max)), j, k1, k2, ctypes.byref(x))
+    r = lib().orc_box_attempt(ctypes.byref(tables(dist, i_max, accel)), j, k1, k2, ctypes.byref(x))
     if r < 0:
         raise ValueError("bad box attempt")
     return bool(r), x.value
 
 
-def box_grid(dist, i_max, j, g, shift):
+def box_grid(dist, i_max, j, g, shift, accel=False):
     """Attempts of box j over the g x g lattice (a << shift, c << shift)."""
     acc = np.empty(g * g, dtype=np.uint8)
     x = np.empty(g * g, dtype=np.float64)
-    r = lib().orc_box_grid(ctypes.byref(tables(dist, i_max)), j, g, shift, acc.ctypes.data, x.ctypes.data)
+    r = lib().orc_box_grid(ctypes.byref(tables(dist, i_max, accel)), j, g, shift, acc.ctypes.data,
+                           x.ctypes.data)
     if r != 0:
         raise ValueError("bad box grid")
     return acc.reshape(g, g).astype(bool), x.reshape(g, g)
 
 
-def sample_region(dist, j, seed, index0, n, i_max=256):
+def sample_region(dist, j, seed, index0, n, i_max=256, accel=False):
     out = np.empty(n, dtype=np.float64)
-    ex, nt = _tabs(dist, i_max)
+    ex, nt = _tabs(dist, i_max, accel)
     r = lib().orc_sample_region(ex, nt, dist, j, seed, index0, n, out.ctypes.data)
     if r != 0:
         raise ValueError("bad region")

@@ -349,6 +349,46 @@ int orc_build_tables(int dist, uint32_t i_max, orc_tables* t) {
     t->K_eps = (uint64_t)floorq((1 - eps) * ldexpq(1, 53));
     hpstr(t->hp_eps, eps);
   }
+  /* chord bands of the normal boxes, for the accelerated overhang variant.
+   * In a box's normalised coordinates the curve runs from (0, 1) to (1, 0)
+   * and the chord is u + v = 1.  Right of the inflection point (X_j >= 1)
+   * the curve is convex and lies below the chord, left of it (X_{j-1} <= 1,
+   * the cap included) concave and above; the gap is largest where the
+   * curve's normalised slope is -1, i.e. where x e^{-x^2/2} = h / w, the
+   * only such point in the box (x e^{-x^2/2} is monotone on either side
+   * of 1).  The box straddling 1 has no band. */
+  if (dist == ORC_NORMAL) {
+    hp ecvx = 0, dccv = 0;
+    for (uint32_t j = 1; j <= L; ++j) {
+      const int convex = t->X[j] >= 1.0, concave = t->X[j - 1] <= 1.0;
+      if (!convex && !concave) continue;
+      const hp left = Xh[j], right = Xh[j - 1], w = right - left;
+      const hp base = fh[j - 1], top = fh[j], h = top - base;
+      const hp target = h / w;
+      hp lo = left, hi = right;
+      for (int it = 0; it < 1000; ++it) {
+        const hp mid = (lo + hi) / 2;
+        if (mid <= lo || mid >= hi) break;
+        const hp ph = mid * expq(-mid * mid / 2) - target;
+        if (convex ? ph > 0 : ph < 0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const hp u = (lo - left) / w;
+      const hp c = (expq(-lo * lo / 2) - base) / h;
+      const hp gap = convex ? (1 - u) - c : c - (1 - u);
+      if (convex && gap > ecvx) ecvx = gap;
+      if (concave && gap > dccv) dccv = gap;
+    }
+    const hp widen = 1 + ldexpq(1, -20);
+    t->eps_cvx = (double)ecvx;
+    t->del_ccv = (double)dccv;
+    t->K_cvx = (uint64_t)floorq((1 - ecvx * widen) * ldexpq(1, 53));
+    t->K_ccv = (uint64_t)ceilq((1 + dccv * widen) * ldexpq(1, 53));
+    hpstr(t->hp_eps_cvx, ecvx);
+    hpstr(t->hp_del_ccv, dccv);
+  }
   t->X0 = t->X[0];
   t->invX0 = (double)(1 / Xh[0]);
   return 0;
@@ -371,7 +411,8 @@ static double box_left(const orc_tables* t, uint32_t j) { return t->X[j]; /* X[L
 
 /* One attempt in box j.  Exponential: reflect across the chord, accept
  * below the eps band without evaluating P, else compare with P(x).
- * Normal: compare with P(x). */
+ * Normal: compare with P(x); in the accelerated variant, first the chord
+ * bands of the convex and concave boxes. */
 static int box_try(const orc_tables* t, uint32_t j, uint64_t k1, uint64_t k2, double* x, uint32_t* tests) {
   if (t->dist == ORC_EXP) {
     if (k1 + k2 > ONE53) {
@@ -392,6 +433,46 @@ static int box_try(const orc_tables* t, uint32_t j, uint64_t k1, uint64_t k2, do
       return 1;
     }
     return 0;
+  }
+  if (t->accel) {
+    /* accelerated variant: reflection and the eps band in convex boxes,
+     * accept below the chord and reject above the delta band in concave
+     * ones, plain rejection in the box straddling the inflection point */
+    if (t->X[j] >= 1.0) {
+      if (k1 + k2 > ONE53) {
+        uint64_t r1 = ONE53 - k2;
+        uint64_t r2 = ONE53 - k1;
+        k1 = r1;
+        k2 = r2;
+      }
+      double xv = fma(unif53(k1), t->W[j], box_left(t, j));
+      if (k1 + k2 <= t->K_cvx) {
+        *x = xv;
+        return 1;
+      }
+      double y = fma(unif53(k2), t->H[j], t->f[j - 1]);
+      *tests += 1;
+      if (y < exp(-0.5 * (xv * xv))) {
+        *x = xv;
+        return 1;
+      }
+      return 0;
+    }
+    if (t->X[j - 1] <= 1.0) {
+      double xv = fma(unif53(k1), t->W[j], box_left(t, j));
+      if (k1 + k2 <= ONE53) {
+        *x = xv;
+        return 1;
+      }
+      if (k1 + k2 > t->K_ccv) return 0;
+      double y = fma(unif53(k2), t->H[j], t->f[j - 1]);
+      *tests += 1;
+      if (y < exp(-0.5 * (xv * xv))) {
+        *x = xv;
+        return 1;
+      }
+      return 0;
+    }
   }
   double xv = fma(unif53(k1), t->W[j], box_left(t, j));
   double y = fma(unif53(k2), t->H[j], t->f[j - 1]);
@@ -608,6 +689,125 @@ int orc_fill(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, ui
   }
   for (int k = 0; k < threads; ++k) pthread_create(&tid[k], NULL, fill_worker, &jobs[k]);
   for (int k = 0; k < threads; ++k) pthread_join(tid[k], NULL);
+  return 0;
+}
+
+/* ---- raw moments in a fixed summation order ----------------------------
+ * The sums S_p = sum over outputs of x^p, p = 1..5, of the outputs a fill
+ * of (dist, dtype, seed, first, n, scale, shift) would write, each x taken
+ * as written (double, or float widened to double) and its powers formed as
+ * q1 = x, q2 = x*x, q3 = q2*x, q4 = q2*q2, q5 = q4*x.  The order of the
+ * additions is part of the definition, so that any implementation of it
+ * gets the same bits:
+ *   - blocks of `per` outputs (2 for FP64, 4 for FP32), numbered from
+ *     blk0 = first / per; tiles of 2048 blocks from blk0;
+ *   - in a tile, lane l (0..255) adds, from +0, the powers of the outputs of
+ *     blocks l, l + 256, ..., l + 7*256 of the tile, each block's outputs in
+ *     order, skipping outputs outside [first, first + n - 1];
+ *   - the 256 lane sums are reduced by halving: for s = 128, 64, ..., 1,
+ *     v[l] = v[l] + v[l + s] for l < s; the tile sum is v[0];
+ *   - groups of 256 consecutive tiles (the last one padded with +0) are
+ *     reduced the same way;
+ *   - the total is +0 plus the group sums, one after the other in order. */
+#define MOM_TILE_BLOCKS 2048u
+#define MOM_LANES 256u
+
+static void halving_sum(double v[][5], uint32_t width) {
+  for (uint32_t s = width / 2; s >= 1; s /= 2)
+    for (uint32_t l = 0; l < s; ++l)
+      for (int p = 0; p < 5; ++p) v[l][p] = v[l][p] + v[l + s][p];
+}
+
+typedef struct {
+  int dist, dtype;
+  const orc_tables *ex, *nt;
+  uint64_t seed, first, last, blk0, t_lo, t_hi;
+  double scale, shift;
+  double* tile_sums; /* [tiles][5] */
+} mom_job;
+
+static void* mom_worker(void* arg) {
+  mom_job* jb = (mom_job*)arg;
+  const uint64_t per = jb->dtype == ORC_F64 ? 2 : 4;
+  static __thread double lanes[MOM_LANES][5];
+  for (uint64_t t = jb->t_lo; t < jb->t_hi; ++t) {
+    for (uint32_t l = 0; l < MOM_LANES; ++l) {
+      double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (uint32_t s = 0; s < MOM_TILE_BLOCKS / MOM_LANES; ++s) {
+        const uint64_t b = jb->blk0 + t * MOM_TILE_BLOCKS + l + (uint64_t)MOM_LANES * s;
+        for (uint64_t o = 0; o < per; ++o) {
+          const uint64_t g = b * per + o;
+          if (g < jb->first || g > jb->last) continue;
+          trace_rec tr;
+          double x;
+          if (jb->dtype == ORC_F64)
+            x = sample64(jb->dist, jb->ex, jb->nt, jb->seed, g, jb->scale, jb->shift, &tr);
+          else
+            x = (double)sample32(jb->dist, jb->ex, jb->nt, jb->seed, g, jb->scale, jb->shift, &tr);
+          const double q2 = x * x, q3 = q2 * x, q4 = q2 * q2, q5 = q4 * x;
+          a[0] = a[0] + x;
+          a[1] = a[1] + q2;
+          a[2] = a[2] + q3;
+          a[3] = a[3] + q4;
+          a[4] = a[4] + q5;
+        }
+      }
+      for (int p = 0; p < 5; ++p) lanes[l][p] = a[p];
+    }
+    halving_sum(lanes, MOM_LANES);
+    for (int p = 0; p < 5; ++p) jb->tile_sums[t * 5 + p] = lanes[0][p];
+  }
+  return NULL;
+}
+
+int orc_moments(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, uint64_t seed, uint64_t first,
+                uint64_t n, double scale, double shift, double sums[5], int threads) {
+  double dummy;
+  if (check_args(dist, dtype, ex, nt, first, n, &dummy) || sums == NULL) return -1;
+  for (int p = 0; p < 5; ++p) sums[p] = 0.0;
+  if (n == 0) return 0;
+  const uint64_t per = dtype == ORC_F64 ? 2 : 4;
+  const uint64_t last = first + (n - 1);
+  const uint64_t blk0 = first / per;
+  const uint64_t blocks = last / per - blk0 + 1;
+  const uint64_t tiles = (blocks + MOM_TILE_BLOCKS - 1) / MOM_TILE_BLOCKS;
+  double* tile_sums = (double*)malloc(tiles * 5 * sizeof(double));
+  if (tile_sums == NULL) return -1;
+  if (threads < 1) threads = 1;
+  if (threads > 256) threads = 256;
+  if ((uint64_t)threads > tiles) threads = (int)tiles;
+  mom_job jobs[256];
+  pthread_t tid[256];
+  for (int k = 0; k < threads; ++k) {
+    mom_job* jb = &jobs[k];
+    jb->dist = dist;
+    jb->dtype = dtype;
+    jb->ex = ex;
+    jb->nt = nt;
+    jb->seed = seed;
+    jb->first = first;
+    jb->last = last;
+    jb->blk0 = blk0;
+    jb->t_lo = tiles * (uint64_t)k / (uint64_t)threads;
+    jb->t_hi = tiles * (uint64_t)(k + 1) / (uint64_t)threads;
+    jb->scale = scale;
+    jb->shift = shift;
+    jb->tile_sums = tile_sums;
+  }
+  if (threads == 1) {
+    mom_worker(&jobs[0]);
+  } else {
+    for (int k = 0; k < threads; ++k) pthread_create(&tid[k], NULL, mom_worker, &jobs[k]);
+    for (int k = 0; k < threads; ++k) pthread_join(tid[k], NULL);
+  }
+  double group[MOM_LANES][5];
+  for (uint64_t g0 = 0; g0 < tiles; g0 += MOM_LANES) {
+    for (uint32_t i = 0; i < MOM_LANES; ++i)
+      for (int p = 0; p < 5; ++p) group[i][p] = (g0 + i < tiles) ? tile_sums[(g0 + i) * 5 + p] : 0.0;
+    halving_sum(group, MOM_LANES);
+    for (int p = 0; p < 5; ++p) sums[p] = sums[p] + group[0][p];
+  }
+  free(tile_sums);
   return 0;
 }
 

@@ -50,12 +50,22 @@ typedef struct {
   double eps;                  /* exp only: max normalised chord gap */
   uint64_t K_eps;              /* exp only: floor((1 - eps) * 2^53) */
   double X0, invX0;
+  /* normal only, for the accelerated overhang variant: the largest
+   * normalised gap between chord and curve in the convex boxes (X_j >= 1,
+   * curve below the chord) and in the concave boxes (X_{j-1} <= 1, curve
+   * above), each widened by 2^-20 relatively, as integer thresholds on
+   * k1 + k2: K_cvx = floor((1 - eps_cvx) 2^53), K_ccv = ceil((1 + del_ccv) 2^53). */
+  double eps_cvx, del_ccv;
+  uint64_t K_cvx, K_ccv;
+  /* normal only: 1 selects the accelerated overhang variant (set by the
+   * caller after building; 0 = plain rejection, the default) */
+  int accel;
   /* decimal strings (36 significant digits) of the 113-bit values, for
    * the tests that check the construction in higher precision */
   char hpX[ORC_MAX_IMAX + 1][48];
   char hpf[ORC_MAX_IMAX + 1][48];
   char hpA[ORC_MAX_IMAX + 1][48];
-  char hp_area[48], hp_total[48], hp_eps[48];
+  char hp_area[48], hp_total[48], hp_eps[48], hp_eps_cvx[48], hp_del_ccv[48];
 } orc_tables;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) */
@@ -82,6 +92,14 @@ int orc_fill(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, ui
 int orc_fill_trace(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, uint64_t seed,
                    uint64_t first, uint64_t n, double scale, double shift, void* out, uint32_t* layer,
                    int32_t* region, uint32_t* words, uint32_t* tests);
+
+/* Raw moment sums S_p = sum of x^p, p = 1..5, over the outputs a fill of
+ * the same arguments writes, added in the fixed order described in
+ * zig_oracle.c (lane sums over 2048-block tiles, halving trees over lanes
+ * and over groups of 256 tiles, then the groups in order).  Uses `threads`
+ * POSIX threads over tiles; the result does not depend on it. */
+int orc_moments(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, uint64_t seed, uint64_t first,
+                uint64_t n, double scale, double shift, double sums[5], int threads);
 
 /* One rejection attempt in overhang/cap box j (1..L) with injected
  * 53-bit integers k1, k2.  Returns 1 and sets *x on acceptance. */

@@ -132,6 +132,32 @@ int stream_counters(void* stream, uint32_t** out) {
   return ZIG_OK;
 }
 
+// Scratch of zig_moments per (device, stream): per-tile and per-group sums
+// of one segment.  Kept until the process ends.
+struct MomScratch {
+  double* tiles = nullptr;
+  double* groups = nullptr;
+};
+std::map<std::pair<int, void*>, MomScratch> g_mom;
+
+int moments_scratch(void* stream, MomScratch* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_cmu);
+  MomScratch& m = g_mom[std::make_pair(dev, stream)];
+  if (!m.tiles) {
+    e = hipMalloc(&m.tiles, (size_t)kMomSegTiles * 5 * sizeof(double));
+    if (e != hipSuccess) return fail(ZIG_ENOMEM, std::string("hipMalloc(moment sums): ") + hipGetErrorString(e));
+  }
+  if (!m.groups) {
+    e = hipMalloc(&m.groups, (size_t)(kMomSegTiles / 256) * 5 * sizeof(double));
+    if (e != hipSuccess) return fail(ZIG_ENOMEM, std::string("hipMalloc(moment sums): ") + hipGetErrorString(e));
+  }
+  *out = m;
+  return ZIG_OK;
+}
+
 int check_params(uint32_t dist, double p0, double p1, double* scale, double* shift) {
   if (dist == kDistExp) {
     if (!std::isfinite(p0) || !(p0 > 0.0)) return fail(ZIG_EINVAL, "lambda must be finite and > 0");
@@ -310,6 +336,71 @@ int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
                    void* stream, const zig_launch* launch) {
   return zig::fill_impl(dist, dtype, seed, first_index, n, p0, p1, out, stream, launch, true, layer, region, words,
                         tests, nullptr);
+}
+
+int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
+                double* sums, void* stream, const zig_launch* launch) {
+  zig::g_error.clear();
+  if (dist > 1) return zig::fail(ZIG_EINVAL, "unknown distribution");
+  if (dtype > 1) return zig::fail(ZIG_EINVAL, "unknown dtype");
+  double scale = 0.0, shift = 0.0;
+  int r = zig::check_params(dist, p0, p1, &scale, &shift);
+  if (r != ZIG_OK) return r;
+  zig_launch cfg = {0, 0, 0};
+  if (launch) cfg = *launch;
+  const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
+  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if ((cfg.wg && cfg.wg != 256) || (cfg.spl && cfg.spl != 8))
+    return zig::fail(ZIG_EINVAL, "the moments kernel runs 256 lanes x 8 blocks (its summation order)");
+  if (sums == nullptr) return zig::fail(ZIG_EINVAL, "sums is null");
+  if (((uintptr_t)sums) % 8 != 0) return zig::fail(ZIG_EINVAL, "sums is not 8-byte aligned");
+  if (n > 0 && n - 1 > UINT64_MAX - first_index) return zig::fail(ZIG_EINVAL, "first_index + n exceeds 2^64");
+  if (n == 0) {
+    const int e = zig::launch_moments_zero(sums, stream);
+    if (e != 0) return zig::fail(ZIG_EHIP, std::string("moments launch: ") + hipGetErrorString((hipError_t)e));
+    return ZIG_OK;
+  }
+  const zig::DevTable* tabs = nullptr;
+  r = zig::device_tables(i_max, &tabs);
+  if (r != ZIG_OK) return r;
+  zig::MomScratch ms;
+  r = zig::moments_scratch(stream, &ms);
+  if (r != ZIG_OK) return r;
+  const uint64_t per_block = dtype == zig::kF64 ? 2 : 4;
+  const uint64_t last = first_index + (n - 1);
+  zig::FillArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.seed = seed;
+  a.first = first_index;
+  a.last = last;
+  a.blk_last = last / per_block;
+  a.out = nullptr;
+  a.scale = scale;
+  a.shift = shift;
+  a.tab = tabs + dist;
+  a.etab = tabs + zig::kDistExp;
+  a.aligned16 = 0;
+  r = zig::stream_counters(stream, &a.counters);
+  if (r != ZIG_OK) return r;
+  a.full_lo = first_index / per_block + (first_index % per_block != 0);
+  if (last % per_block == per_block - 1) {
+    a.full_hi = last / per_block;
+    a.has_full = a.full_lo <= a.full_hi;
+  } else {
+    a.full_hi = last / per_block == 0 ? 0 : last / per_block - 1;
+    a.has_full = last / per_block > 0 && a.full_lo <= a.full_hi;
+  }
+  const uint64_t blk0 = first_index / per_block;
+  const uint64_t nblk = a.blk_last - blk0 + 1;
+  const uint64_t tiles = nblk / zig::kMomTileBlocks + (nblk % zig::kMomTileBlocks != 0);
+  for (uint64_t start = 0; start < tiles; start += zig::kMomSegTiles) {
+    a.blk0 = blk0 + start * zig::kMomTileBlocks;
+    a.tiles = (uint32_t)((tiles - start < zig::kMomSegTiles) ? tiles - start : zig::kMomSegTiles);
+    a.chunk = 8;  // tiles per step of the work counter (16K blocks)
+    const int e = zig::launch_moments_segment(dist, dtype, a, ms.tiles, ms.groups, sums, start > 0, stream);
+    if (e != 0) return zig::fail(ZIG_EHIP, std::string("moments launch: ") + hipGetErrorString((hipError_t)e));
+  }
+  return ZIG_OK;
 }
 
 const char* zig_last_error(void) { return zig::g_error.c_str(); }

@@ -119,8 +119,14 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
 
 // One tile (tile index t of this launch).  Ends with the staging tile
 // written out; callers separate consecutive tiles with a barrier.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE>
-__device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t) {
+//
+// With MOM set, phase C instead reduces the tile to its raw moment sums
+// (S1..S5 into msum[0..4]) in the fixed order of the moments definition:
+// lane l adds the outputs of its blocks l + WG * s in order of s, then the
+// lane sums are reduced by halving.
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool MOM = false>
+__device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t,
+                                          double* msum = nullptr) {
   using Sh = FillShape<DT, WG, S>;
   using OutT = typename Sh::OutT;
   using VecT = typename Sh::VecT;
@@ -298,6 +304,44 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
     }
   }
   __syncthreads();
+
+  if constexpr (MOM) {
+    static_assert(WG == 256 && S == 8, "the moments order is defined on 256 lanes x 8 blocks");
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;
+      const VecT vv = stage[s * WG + tid];
+      const OutT* pv = reinterpret_cast<const OutT*>(&vv);
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        const uint64_t g = m * O + o;
+        if (interior || (m <= a.blk_last && g >= a.first && g <= a.last)) {
+          const double x = (double)pv[o];
+          const double q2 = x * x, q3 = q2 * x, q4 = q2 * q2, q5 = q4 * x;
+          acc[0] = acc[0] + x;
+          acc[1] = acc[1] + q2;
+          acc[2] = acc[2] + q3;
+          acc[3] = acc[3] + q4;
+          acc[4] = acc[4] + q5;
+        }
+      }
+    }
+    __syncthreads();  // every lane has read its blocks; the staging tile is reused
+    double* red = static_cast<double*>(sh.stage);  // [5][WG]
+#pragma unroll
+    for (int p = 0; p < 5; ++p) red[p * WG + tid] = acc[p];
+    __syncthreads();
+    for (uint32_t h = WG / 2; h >= 1; h >>= 1) {
+      if (tid < h) {
+#pragma unroll
+        for (int p = 0; p < 5; ++p) red[p * WG + tid] = red[p * WG + tid] + red[p * WG + tid + h];
+      }
+      __syncthreads();
+    }
+    if (tid < 5) msum[tid] = red[tid * WG];
+    return;
+  }
 
   // C: staging tile to HBM
 #pragma unroll

@@ -78,6 +78,16 @@ struct FillArgs {
 int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, const FillArgs& a,
                 void* stream);
 
+// Raw moments (zig_moments.hip): one segment of at most kMomSegTiles tiles
+// of 2048 blocks (a.tiles, a.blk0 set by the caller); tile_sums holds
+// 5 * kMomSegTiles doubles, group_sums 5 * kMomSegTiles / 256.  Returns 0 or
+// a hipError_t value.
+constexpr uint32_t kMomTileBlocks = 2048;
+constexpr uint32_t kMomSegTiles = 1u << 16;
+int launch_moments_segment(uint32_t dist, uint32_t dtype, const FillArgs& a, double* tile_sums, double* group_sums,
+                           double* sums, bool accumulate, void* stream);
+int launch_moments_zero(double* sums, void* stream);
+
 // One request of a batch as the batch kernel reads it (device memory).
 struct BatchReq {
   uint64_t seed, first, last, blk0, blk_last, full_lo, full_hi;

@@ -135,11 +135,12 @@ _server_set_counters = _sig("zig_server_set_counters", i32, [_srv_p, vp, u32])
 _server_stats = _sig("zig_server_stats_get", i32, [_srv_p, ctypes.POINTER(ServerStats)])
 _server_replay = _sig("zig_server_replay", i32, [_srv_p, vp, u64, u32, vp])
 _server_destroy = _sig("zig_server_destroy", i32, [_srv_p])
+_moments = _sig("zig_moments", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, ctypes.POINTER(Launch)])
 _last_error = _sig("zig_last_error", ctypes.c_char_p, [])
 _version = _sig("zig_version", ctypes.c_char_p, [])
 
 EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
-           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_autotune", "zig_tuned_shape",
+           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_moments", "zig_autotune", "zig_tuned_shape",
            "zig_tuned_batch_shape", "zig_autotune_reset", "zig_server_now_ns", "zig_server_create",
            "zig_server_submit", "zig_server_wait", "zig_server_release", "zig_server_drop_client",
            "zig_server_counters", "zig_server_set_counters", "zig_server_stats_get", "zig_server_replay",
@@ -220,6 +221,10 @@ def zig_fill_each(reqs, stream_ptr=None):
     if not isinstance(reqs, ctypes.Array):
         reqs = (Request * len(reqs))(*reqs)
     _check(_fill_each(reqs, len(reqs), stream_ptr))
+
+
+def zig_moments(dist, dtype, seed, first_index, n, p0, p1, sums_ptr, stream_ptr=None, launch=None):
+    _check(_moments(dist, dtype, seed, first_index, n, p0, p1, sums_ptr, stream_ptr, _launch(launch)))
 
 
 def zig_autotune(cache_path=None, flags=0):
@@ -394,6 +399,16 @@ def fill_trace(out, dist, seed, first_index=0, p0=1.0, p1=1.0, launch=None, stre
     zig_fill_trace(dist, _dtype_code(out), seed, first_index, n, p0, p1, out.data_ptr(), layer.data_ptr(),
                    region.data_ptr(), words.data_ptr(), tests.data_ptr(), _stream_ptr(stream), launch)
     return out, layer, region, words, tests
+
+
+def moments(dist, dtype, n, seed, first_index=0, p0=1.0, p1=1.0, stream=None, i_max=0):
+    """Raw moment sums S1..S5 of the n outputs (dtype F64 or F32) as a
+    float64 device tensor of 5 elements; nothing else is written."""
+    import torch
+    sums = torch.empty(5, dtype=torch.float64, device="cuda")
+    zig_moments(dist, dtype, seed, first_index, n, p0, p1, sums.data_ptr(), _stream_ptr(stream),
+                Launch(i_max, 0, 0) if i_max else None)
+    return sums
 
 
 def fill_batch(items, stream=None, opts=None):
