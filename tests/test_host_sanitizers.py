@@ -15,8 +15,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1403_6870_amd", "csrc")
 BUILD = os.path.join(ROOT, "paper_1403_6870_amd", "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
-HOST = ["zig_tables.cpp", "zig_tune.cpp", "zig_api.cpp", "zig_batch.cpp", "zig_server.cpp"]
-DEVICE_OBJS = [os.path.join(BUILD, "zig_fill.hip.o"), os.path.join(BUILD, "zig_batch.hip.o")]
+from paper_1403_6870_amd import build_lib  # noqa: E402  (source lists only; builds nothing on import)
+
+HOST = list(build_lib.HOST_SRCS)
+DEVICE_OBJS = [os.path.join(BUILD, s + ".o") for s in build_lib.HIP_SRCS]
 
 
 def _run(cmd, **kw):
