@@ -280,7 +280,7 @@ def moments_bench(torch, zig):
     for name, dist, want in [("exp", 0, [1, 2, 6, 24, 120]), ("normal", 1, [0, 1, 0, 3, 0])]:
         n = 10 ** 12
         t0 = time.perf_counter()
-        s = zig.moments(dist, 0, n, 2014, 0, 1.0, 1.0).cpu().numpy()
+        s = zig.moments(dist, 0, n, 2014, 0, *((1.0, 0.0) if dist == 0 else (0.0, 1.0))).cpu().numpy()
         secs = time.perf_counter() - t0
         appb[name] = {"draws": n, "seconds": round(secs, 2), "moments": [float(v / n) for v in s],
                       "closed_form": want}
@@ -422,6 +422,15 @@ def main():
             extra[name] = {"Gsamples/s": round(N_C3 / (ms * 1e-3) / 1e9, 2), "kernel_ms": round(ms, 4),
                            "GB/s": round(N_C3 * 4 / (ms * 1e-3) / 1e9, 1)}
         del o32
+        # the accelerated normal-overhang variant at the headline size
+        out = torch.empty(N_C3, dtype=torch.float64, device=dev)
+        lac = zig.Launch(0, 0, 0, zig.LAUNCH_NORMAL_ACCEL)
+        w, dd = timed_fills(torch, zig, [(lambda: zig.fill(out, 1, 12, 0, -1.0, 3.0, launch=lac), N_C3 * 8)], 10, 3)
+        ms = float(np.mean(dd))
+        extra["normal_2^30_f64_accel_variant"] = {"Gsamples/s": round(N_C3 / (ms * 1e-3) / 1e9, 2),
+                                                  "kernel_ms": round(ms, 4),
+                                                  "GB/s": round(N_C3 * 8 / (ms * 1e-3) / 1e9, 1)}
+        del out
         torch.cuda.empty_cache()
         log("extra: %s" % json.dumps(extra))
         result["other_configs"] = extra

@@ -79,6 +79,12 @@ int zig_build_tables(uint32_t i_max);
  *   eps, K_eps  exponential only: the widest normalised band between a
  *             box's chord and the density, and floor((1 - eps) 2^53)
  *   X0, invX0 tail start and RN(1/X0).
+ *   eps_cvx, del_ccv, K_cvx, K_ccv  normal only, for the accelerated
+ *             overhang variant (ZIG_LAUNCH_NORMAL_ACCEL): the widest
+ *             normalised chord-curve gap of the convex boxes (X_j >= 1)
+ *             and of the concave ones (X_{j-1} <= 1), and the thresholds
+ *             floor((1 - eps_cvx (1 + 2^-20)) 2^53) and
+ *             ceil((1 + del_ccv (1 + 2^-20)) 2^53) on k1 + k2.
  * Builds the tables if needed.  Errors: ZIG_EINVAL, ZIG_ENOTABLES. */
 typedef struct {
   uint32_t dist, i_max, b, L;
@@ -94,6 +100,8 @@ typedef struct {
   double eps;
   uint64_t K_eps;
   double X0, invX0;
+  double eps_cvx, del_ccv;
+  uint64_t K_cvx, K_ccv;
 } zig_table_view;
 int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out);
 
@@ -116,15 +124,29 @@ int zig_fill_exp(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dtype
 int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dtype, double mu, double sigma,
                     void* out, void* stream);
 
-/* Launch shape and table size for zig_fill.  Zero fields mean "pick":
- * i_max 256; wg/spl from the tuned table.  wg in {64,...,1024} lanes
- * per workgroup and spl in {1,2,4,8} Philox blocks per lane make a tile
- * of wg * spl blocks (at most 2048), which is also the depth of the
- * per-workgroup slow-output queue. */
+/* Launch shape, table size and variant for zig_fill.  Zero fields mean
+ * "pick": i_max 256; wg/spl from the tuned table.  wg in {64,...,1024}
+ * lanes per workgroup and spl in {1,2,4,8} Philox blocks per lane make a
+ * tile of wg * spl blocks (at most 2048), which is also the depth of the
+ * per-workgroup slow-output queue.
+ * flags: ZIG_LAUNCH_NORMAL_ACCEL selects, for the normal distribution, an
+ * accelerated overhang sampler that goes beyond the paper's text (which
+ * gives the chord split for the exponential only, section 2): in the
+ * boxes right of the inflection point x = 1 the density is convex, points
+ * above the chord are reflected across it and points below the band
+ * k1 + k2 <= K_cvx accepted without evaluating it; in the boxes left of
+ * it (and the cap) the density is concave, points on or below the chord
+ * are accepted and points with k1 + k2 > K_ccv rejected without
+ * evaluating it; the box containing x = 1 keeps plain rejection.  Its
+ * outputs are a different exact sample than the default's (the slow
+ * outputs differ; fast-path and tail outputs are the same); the
+ * exponential ignores the flag. */
+#define ZIG_LAUNCH_NORMAL_ACCEL 1u /* normal overhangs: the accelerated variant (see below) */
 typedef struct {
   uint32_t i_max;
   uint32_t wg;
   uint32_t spl;
+  uint32_t flags;
 } zig_launch;
 
 /* Generic fill: dist ZIG_EXP (p0 = lambda, p1 ignored) or ZIG_NORMAL

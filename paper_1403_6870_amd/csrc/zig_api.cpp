@@ -57,6 +57,8 @@ void to_device_layout(const HostTable& h, DevTable* d) {
   d->b = h.b;
   d->L = h.L;
   d->K_eps = h.K_eps;
+  d->K_cvx = h.K_cvx;
+  d->K_ccv = h.K_ccv;
   d->X0 = h.X0;
   d->invX0 = h.invX0;
   for (uint32_t i = 0; i < h.i_max; ++i) {
@@ -186,10 +188,11 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   double scale = 0.0, shift = 0.0;
   int r = check_params(dist, p0, p1, &scale, &shift);
   if (r != ZIG_OK) return r;
-  zig_launch cfg = {0, 0, 0};
+  zig_launch cfg = {0, 0, 0, 0};
   if (launch) cfg = *launch;
   const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
   if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (cfg.flags & ~ZIG_LAUNCH_NORMAL_ACCEL) return fail(ZIG_EINVAL, "unknown launch flags");
   if (n == 0) return ZIG_OK;
   if (out == nullptr) return fail(ZIG_EINVAL, "out is null");
   const uint64_t esize = dtype == kF64 ? 8 : 4;
@@ -226,6 +229,7 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   a.tab = tabs + dist;
   a.etab = tabs + kDistExp;
   a.aligned16 = ((((uintptr_t)out) - first * esize) & 15u) == 0 ? 1u : 0u;
+  a.accel = (dist == kDistNormal && (cfg.flags & ZIG_LAUNCH_NORMAL_ACCEL)) ? 1u : 0u;
   a.t_layer = t_layer;
   a.t_region = t_region;
   a.t_words = t_words;
@@ -310,6 +314,10 @@ int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out) {
   out->K_eps = t.K_eps;
   out->X0 = t.X0;
   out->invX0 = t.invX0;
+  out->eps_cvx = t.eps_cvx;
+  out->del_ccv = t.del_ccv;
+  out->K_cvx = t.K_cvx;
+  out->K_ccv = t.K_ccv;
   return ZIG_OK;
 }
 
@@ -346,10 +354,11 @@ int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_ind
   double scale = 0.0, shift = 0.0;
   int r = zig::check_params(dist, p0, p1, &scale, &shift);
   if (r != ZIG_OK) return r;
-  zig_launch cfg = {0, 0, 0};
+  zig_launch cfg = {0, 0, 0, 0};
   if (launch) cfg = *launch;
   const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
   if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (cfg.flags & ~ZIG_LAUNCH_NORMAL_ACCEL) return zig::fail(ZIG_EINVAL, "unknown launch flags");
   if ((cfg.wg && cfg.wg != 256) || (cfg.spl && cfg.spl != 8))
     return zig::fail(ZIG_EINVAL, "the moments kernel runs 256 lanes x 8 blocks (its summation order)");
   if (sums == nullptr) return zig::fail(ZIG_EINVAL, "sums is null");
@@ -380,6 +389,7 @@ int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_ind
   a.tab = tabs + dist;
   a.etab = tabs + zig::kDistExp;
   a.aligned16 = 0;
+  a.accel = (dist == zig::kDistNormal && (cfg.flags & ZIG_LAUNCH_NORMAL_ACCEL)) ? 1u : 0u;
   r = zig::stream_counters(stream, &a.counters);
   if (r != ZIG_OK) return r;
   a.full_lo = first_index / per_block + (first_index % per_block != 0);

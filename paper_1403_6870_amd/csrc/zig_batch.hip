@@ -127,6 +127,8 @@ __global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
       a.has_full = q.has_full;
       a.full_lo = q.full_lo;
       a.full_hi = q.full_hi;
+      a.accel = 0;
+      a.pad = 0;
       a.t_layer = nullptr;
       a.t_region = nullptr;
       a.t_words = nullptr;

@@ -79,6 +79,7 @@ struct TabView {
   const double* XS;
   uint32_t L, imask, b;
   uint64_t keps;
+  uint64_t kcvx, kccv;  // normal: chord-band thresholds of the accelerated variant
   double X0, invX0;
 };
 
@@ -93,6 +94,8 @@ __device__ __forceinline__ TabView global_view(const DevTable* t) {
   v.imask = t->i_max - 1;
   v.b = t->b;
   v.keps = t->K_eps;
+  v.kcvx = t->K_cvx;
+  v.kccv = t->K_ccv;
   v.X0 = t->X0;
   v.invX0 = t->invX0;
   return v;
@@ -174,6 +177,7 @@ __device__ __forceinline__ double exp_from_word(const TabView& E, uint64_t w, Sl
 // Marsaglia's method with two exponential draws E1, E2 (t = E1 / X_0,
 // accept when 2 E2 > t^2, return X_0 + t); a box is sampled by plain
 // rejection against e^{-x^2/2}, retrying in the same box.
+template <bool ACCEL>
 __device__ __forceinline__ double normal_slow(const TabView& N, const TabView& E, SlowStream& s,
                                               int32_t& first_region, uint32_t& tests) {
   const uint32_t j = alias_region(N, s.next());
@@ -189,10 +193,36 @@ __device__ __forceinline__ double normal_slow(const TabView& N, const TabView& E
   const double left = N.X[j], right = N.X[j - 1];
   const double base = N.f[j - 1], top = N.f[j];
   const double width = right - left, height = top - base;
+  if constexpr (!ACCEL) {
+    for (;;) {
+      const uint64_t k1 = s.next() >> 11;
+      const uint64_t k2 = s.next() >> 11;
+      const double x = __builtin_fma(lattice53(k1), width, left);
+      const double yy = __builtin_fma(lattice53(k2), height, base);
+      ++tests;
+      if (yy < exp(-0.5 * (x * x))) return x;
+    }
+  }
+  // accelerated variant: convex boxes (right of the inflection point, curve
+  // below the chord) reflect points above the chord and accept below the
+  // eps band; concave boxes (left of it, the cap included) accept below the
+  // chord and reject above the delta band; the box straddling the
+  // inflection point keeps plain rejection
+  const uint32_t kind = left >= 1.0 ? 1u : right <= 1.0 ? 2u : 0u;
   for (;;) {
-    const uint64_t k1 = s.next() >> 11;
-    const uint64_t k2 = s.next() >> 11;
+    uint64_t k1 = s.next() >> 11;
+    uint64_t k2 = s.next() >> 11;
+    if (kind == 1u && k1 + k2 > kOne53) {
+      const uint64_t r1 = kOne53 - k2;
+      k2 = kOne53 - k1;
+      k1 = r1;
+    }
     const double x = __builtin_fma(lattice53(k1), width, left);
+    if (kind == 1u && k1 + k2 <= N.kcvx) return x;
+    if (kind == 2u) {
+      if (k1 + k2 <= kOne53) return x;
+      if (k1 + k2 > N.kccv) continue;
+    }
     const double yy = __builtin_fma(lattice53(k2), height, base);
     ++tests;
     if (yy < exp(-0.5 * (x * x))) return x;
@@ -201,7 +231,7 @@ __device__ __forceinline__ double normal_slow(const TabView& N, const TabView& E
 
 // Magnitude of output g on its slow path.  `own` is the distribution's
 // table view, `ex` the exponential one (the normal tail).
-template <uint32_t DIST>
+template <uint32_t DIST, bool ACCEL = false>
 __device__ __forceinline__ double slow_magnitude(const TabView& own, const TabView& ex, uint64_t g, uint32_t k0,
                                                  uint32_t k1, int32_t& region, uint32_t& words, uint32_t& tests) {
   SlowStream s(g, k0, k1);
@@ -210,7 +240,7 @@ __device__ __forceinline__ double slow_magnitude(const TabView& own, const TabVi
   if constexpr (DIST == kDistExp)
     m = exp_slow(own, s, region, tests);
   else
-    m = normal_slow(own, ex, s, region, tests);
+    m = normal_slow<ACCEL>(own, ex, s, region, tests);
   words = s.t;
   return m;
 }

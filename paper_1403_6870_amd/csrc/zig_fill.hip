@@ -36,9 +36,9 @@ int resident_groups(K kernel, int wg, size_t lds, int* out) {
   return 0;
 }
 
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE>
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL>
 int launch_one(const FillArgs& args, hipStream_t st) {
-  auto kernel = fill_kernel<DIST, DT, WG, S, TRACE>;
+  auto kernel = fill_kernel<DIST, DT, WG, S, TRACE, ACCEL>;
   int groups = 0;
   int e = resident_groups(kernel, WG, 0, &groups);
   if (e != 0) return e;
@@ -55,10 +55,10 @@ int launch_one(const FillArgs& args, hipStream_t st) {
   return (int)hipGetLastError();
 }
 
-template <uint32_t DIST, uint32_t DT, bool TRACE>
+template <uint32_t DIST, uint32_t DT, bool TRACE, bool ACCEL = false>
 int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
 #define ZIG_SHAPE(W, S_) \
-  if (wg == W && spl == S_) return launch_one<DIST, DT, W, S_, TRACE>(a, st);
+  if (wg == W && spl == S_) return launch_one<DIST, DT, W, S_, TRACE, ACCEL>(a, st);
   if constexpr (!TRACE) {
     ZIG_SHAPE(64, 1) ZIG_SHAPE(64, 2) ZIG_SHAPE(64, 4) ZIG_SHAPE(64, 8)
     ZIG_SHAPE(128, 1) ZIG_SHAPE(128, 2) ZIG_SHAPE(128, 4) ZIG_SHAPE(128, 8)
@@ -77,6 +77,16 @@ int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
 int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, const FillArgs& a,
                 void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dist == kDistNormal && a.accel) {  // the accelerated overhang variant
+    if (trace) {
+      if (dtype == kF64) return launch_shape<kDistNormal, kF64, true, true>(wg, spl, a, st);
+      if (dtype == kF32) return launch_shape<kDistNormal, kF32, true, true>(wg, spl, a, st);
+    } else {
+      if (dtype == kF64) return launch_shape<kDistNormal, kF64, false, true>(wg, spl, a, st);
+      if (dtype == kF32) return launch_shape<kDistNormal, kF32, false, true>(wg, spl, a, st);
+    }
+    return (int)hipErrorInvalidValue;
+  }
   if (trace) {
     if (dist == kDistExp && dtype == kF64) return launch_shape<kDistExp, kF64, true>(wg, spl, a, st);
     if (dist == kDistExp && dtype == kF32) return launch_shape<kDistExp, kF32, true>(wg, spl, a, st);

@@ -124,7 +124,7 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
 // (S1..S5 into msum[0..4]) in the fixed order of the moments definition:
 // lane l adds the outputs of its blocks l + WG * s in order of s, then the
 // lane sums are reduced by halving.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool MOM = false>
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool MOM = false, bool ACCEL = false>
 __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t,
                                           double* msum = nullptr) {
   using Sh = FillShape<DT, WG, S>;
@@ -282,7 +282,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
     if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, c.k0, c.k1);
     int32_t region;
     uint32_t words, tests;
-    const double mag = dev::slow_magnitude<DIST>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
+    const double mag = dev::slow_magnitude<DIST, ACCEL>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
     OutT x = (OutT)mag;
     if (neg) x = -x;
     if constexpr (DIST == kDistExp) {
@@ -332,14 +332,28 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
 #pragma unroll
     for (int p = 0; p < 5; ++p) red[p * WG + tid] = acc[p];
     __syncthreads();
-    for (uint32_t h = WG / 2; h >= 1; h >>= 1) {
-      if (tid < h) {
+    if (tid < 128) {  // level 128 across waves
 #pragma unroll
-        for (int p = 0; p < 5; ++p) red[p * WG + tid] = red[p * WG + tid] + red[p * WG + tid + h];
-      }
-      __syncthreads();
+      for (int p = 0; p < 5; ++p) red[p * WG + tid] = red[p * WG + tid] + red[p * WG + tid + 128];
     }
-    if (tid < 5) msum[tid] = red[tid * WG];
+    __syncthreads();
+    if (tid < 64) {  // level 64, then 32 .. 1 inside wave 0 (the same pairs)
+      double v[5];
+#pragma unroll
+      for (int p = 0; p < 5; ++p) v[p] = red[p * WG + tid] + red[p * WG + tid + 64];
+#pragma unroll
+      for (int h = 32; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+          const double up = __shfl_down(v[p], h);
+          if ((int)tid < h) v[p] = v[p] + up;
+        }
+      }
+      if (tid == 0) {
+#pragma unroll
+        for (int p = 0; p < 5; ++p) msum[p] = v[p];
+      }
+    }
     return;
   }
 
@@ -373,7 +387,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
 // device on that address), so the tiles in flight stay a window that
 // sweeps through the output in address order.  The last workgroup to leave
 // resets the counters for the next launch on the same stream.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE>
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false>
 __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
   __shared__ FillLds<DT, WG, S> sh;
   const FillCtx c = load_tables<DIST, DT, WG, S>(a, sh);
@@ -388,7 +402,7 @@ __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
     if (t0 >= a.tiles) break;
     const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
     for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, WG, S, TRACE>(a, c, tl, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE, false, ACCEL>(a, c, tl, (uint32_t)t);
       __syncthreads();
     }
   }

@@ -19,6 +19,7 @@ constexpr uint32_t kF32 = 1;
 struct DevTable {
   uint32_t dist, i_max, b, L;
   uint64_t K_eps;
+  uint64_t K_cvx, K_ccv;  // normal: chord-band thresholds of the accelerated overhang variant
   double X0, invX0;
   double XS[kMaxLayers];
   float XS32[kMaxLayers];
@@ -31,7 +32,7 @@ struct DevTable {
 };
 
 // g++ builds the host side and hipcc the device side: both must agree
-static_assert(sizeof(DevTable) == 14408, "DevTable layout");
+static_assert(sizeof(DevTable) == 14424, "DevTable layout");
 
 // Host copy with the same content plus the quantities only tests need.
 struct HostTable {
@@ -42,6 +43,8 @@ struct HostTable {
   std::vector<uint32_t> A;
   double eps = 0.0, X0 = 0.0, invX0 = 0.0;
   uint64_t K_eps = 0;
+  double eps_cvx = 0.0, del_ccv = 0.0;  // normal only
+  uint64_t K_cvx = 0, K_ccv = 0;
 };
 
 // Builds one distribution's tables in binary128 (zig_tables.cpp).
@@ -65,6 +68,8 @@ struct FillArgs {
   uint32_t aligned16;    // 16-byte block stores are aligned
   uint32_t has_full;     // some block has all its outputs in range
   uint64_t full_lo, full_hi;  // first and last such block
+  uint32_t accel;        // normal: accelerated overhang variant (chord bands)
+  uint32_t pad;
   // trace arrays (trace build only), indexed by output - first
   uint32_t* t_layer;
   int32_t* t_region;

@@ -27,7 +27,7 @@ namespace {
 constexpr int kMomWG = 256;
 constexpr int kMomS = 8;
 
-template <uint32_t DIST, uint32_t DT>
+template <uint32_t DIST, uint32_t DT, bool ACCEL>
 __global__ void __launch_bounds__(kMomWG) moments_kernel(FillArgs a, double* tile_sums) {
   __shared__ FillLds<DT, kMomWG, kMomS> sh;
   const FillCtx c = load_tables<DIST, DT, kMomWG, kMomS>(a, sh);
@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kMomWG) moments_kernel(FillArgs a, double* til
     if (t0 >= a.tiles) break;
     const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
     for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, kMomWG, kMomS, false, true>(a, c, tl, (uint32_t)t, tile_sums + 5 * t);
+      fill_tile<DIST, DT, kMomWG, kMomS, false, true, ACCEL>(a, c, tl, (uint32_t)t, tile_sums + 5 * t);
       __syncthreads();
     }
   }
@@ -105,9 +105,9 @@ int resident(K kernel, int* out) {
   return 0;
 }
 
-template <uint32_t DIST, uint32_t DT>
+template <uint32_t DIST, uint32_t DT, bool ACCEL = false>
 int launch_segment(const FillArgs& args, double* tile_sums, hipStream_t st) {
-  auto kernel = moments_kernel<DIST, DT>;
+  auto kernel = moments_kernel<DIST, DT, ACCEL>;
   int groups = 0;
   int e = resident(kernel, &groups);
   if (e != 0) return e;
@@ -128,7 +128,10 @@ int launch_moments_segment(uint32_t dist, uint32_t dtype, const FillArgs& a, dou
                            double* sums, bool accumulate, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   int e;
-  if (dist == kDistExp && dtype == kF64)
+  if (dist == kDistNormal && a.accel)
+    e = dtype == kF64 ? launch_segment<kDistNormal, kF64, true>(a, tile_sums, st)
+                      : launch_segment<kDistNormal, kF32, true>(a, tile_sums, st);
+  else if (dist == kDistExp && dtype == kF64)
     e = launch_segment<kDistExp, kF64>(a, tile_sums, st);
   else if (dist == kDistExp && dtype == kF32)
     e = launch_segment<kDistExp, kF32>(a, tile_sums, st);

@@ -224,6 +224,34 @@ std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out) {
     t.eps = (double)eps;
     t.K_eps = (uint64_t)floorq((1 - eps) * 9007199254740992.0Q);
   }
+
+  // normal boxes, for the accelerated overhang variant: the largest
+  // normalised gap between chord and curve in the convex boxes (X_j >= 1,
+  // curve below the chord) and in the concave ones (X_{j-1} <= 1, curve
+  // above, the cap included), at the point where the curve's normalised
+  // slope is -1: x e^{-x^2/2} = h / w.  Each is widened by 2^-20 and turned
+  // into a threshold on k1 + k2.
+  if (dist == kDistNormal) {
+    q128 widest_below = 0, widest_above = 0;
+    for (uint32_t j = 1; j <= L; ++j) {
+      const bool convex = t.X[j] >= 1.0, concave = t.X[j - 1] <= 1.0;
+      if (!convex && !concave) continue;
+      const q128 left = (j == L) ? (q128)0 : Xq[j], right = Xq[j - 1];
+      const q128 base = fq[j - 1], top = (j == L) ? (q128)1 : fq[j];
+      const q128 w = right - left, h = top - base, slope = h / w;
+      auto fn = [&](q128 x) { return x * P.p(x) - slope; };
+      auto dfn = [&](q128 x) { return (1 - x * x) * P.p(x); };
+      const q128 xs = bracketed_newton(fn, dfn, left, right);
+      const q128 u = (xs - left) / w, c = (P.p(xs) - base) / h;
+      if (convex) widest_below = fmaxq(widest_below, (1 - u) - c);
+      if (concave) widest_above = fmaxq(widest_above, c - (1 - u));
+    }
+    const q128 widen = 1 + 0x1p-20Q;
+    t.eps_cvx = (double)widest_below;
+    t.del_ccv = (double)widest_above;
+    t.K_cvx = (uint64_t)floorq((1 - widest_below * widen) * 9007199254740992.0Q);
+    t.K_ccv = (uint64_t)ceilq((1 + widest_above * widen) * 9007199254740992.0Q);
+  }
   t.X0 = t.X[0];
   t.invX0 = (double)(1 / Xq[0]);
   return std::string();

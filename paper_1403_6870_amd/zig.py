@@ -38,11 +38,15 @@ class TableView(ctypes.Structure):
                 ("X", ctypes.POINTER(dbl)), ("f", ctypes.POINTER(dbl)), ("XS", ctypes.POINTER(dbl)),
                 ("XS32", ctypes.POINTER(ctypes.c_float)), ("W", ctypes.POINTER(dbl)), ("H", ctypes.POINTER(dbl)),
                 ("q", ctypes.POINTER(u64)), ("T", ctypes.POINTER(u64)), ("alias", ctypes.POINTER(u32)),
-                ("eps", dbl), ("K_eps", u64), ("X0", dbl), ("invX0", dbl)]
+                ("eps", dbl), ("K_eps", u64), ("X0", dbl), ("invX0", dbl),
+                ("eps_cvx", dbl), ("del_ccv", dbl), ("K_cvx", u64), ("K_ccv", u64)]
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("i_max", u32), ("wg", u32), ("spl", u32)]
+    _fields_ = [("i_max", u32), ("wg", u32), ("spl", u32), ("flags", u32)]
+
+
+LAUNCH_NORMAL_ACCEL = 1
 
 
 class Request(ctypes.Structure):
@@ -165,7 +169,8 @@ def _launch(launch):
         return None
     if isinstance(launch, Launch):
         return ctypes.byref(launch)
-    return ctypes.byref(Launch(launch.get("i_max", 0), launch.get("wg", 0), launch.get("spl", 0)))
+    return ctypes.byref(Launch(launch.get("i_max", 0), launch.get("wg", 0), launch.get("spl", 0),
+                               launch.get("flags", 0)))
 
 
 def zig_build_tables(i_max=256):
@@ -184,6 +189,7 @@ def zig_get_tables(dist, i_max=256):
         "W": arr(v.W, L + 1, np.float64), "H": arr(v.H, L + 1, np.float64),
         "q": arr(v.q, L + 1, np.uint64), "T": arr(v.T, im, np.uint64), "A": arr(v.alias, im, np.uint32),
         "eps": v.eps, "K_eps": int(v.K_eps), "X0": v.X0, "invX0": v.invX0,
+        "eps_cvx": v.eps_cvx, "del_ccv": v.del_ccv, "K_cvx": int(v.K_cvx), "K_ccv": int(v.K_ccv),
     }
 
 

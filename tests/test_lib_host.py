@@ -47,7 +47,7 @@ def test_tables_match_oracle(zig, O, dist, i_max):
         x, y = a[k], b[k]
         assert x.shape == y.shape, k
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), k
-    for k in ["eps", "K_eps", "X0", "invX0"]:
+    for k in ["eps", "K_eps", "X0", "invX0", "eps_cvx", "del_ccv", "K_cvx", "K_ccv"]:
         assert a[k] == b[k], k
 
 
