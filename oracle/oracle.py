@@ -32,6 +32,16 @@ def build(force=False):
     return LIB
 
 
+class Trad(ctypes.Structure):
+    _fields_ = [
+        ("dist", ctypes.c_int), ("n", ctypes.c_uint32), ("b", ctypes.c_uint32),
+        ("X", ctypes.c_double * (MAXI + 1)), ("f", ctypes.c_double * (MAXI + 1)),
+        ("W", ctypes.c_double * MAXI), ("WS", ctypes.c_double * MAXI), ("k", ctypes.c_double * MAXI),
+        ("v", ctypes.c_double), ("r", ctypes.c_double), ("invr", ctypes.c_double),
+        ("hp_r", ctypes.c_char * 48), ("hp_v", ctypes.c_char * 48),
+    ]
+
+
 class Tables(ctypes.Structure):
     _fields_ = [
         ("dist", ctypes.c_int), ("i_max", ctypes.c_uint32), ("b", ctypes.c_uint32), ("L", ctypes.c_uint32),
@@ -78,6 +88,15 @@ def lib():
         L.orc_alias_draw.restype = u32
         L.orc_moments.argtypes = [i32, i32, tp, tp, u64, u64, u64, dbl, dbl, ctypes.POINTER(dbl), i32]
         L.orc_moments.restype = i32
+        trp = ctypes.POINTER(Trad)
+        L.orc_build_trad.argtypes = [i32, u32, trp]
+        L.orc_build_trad.restype = i32
+        L.orc_trad_fill.argtypes = [i32, trp, trp, u64, u64, u64, dbl, dbl, vp, vp, i32]
+        L.orc_trad_fill.restype = i32
+        L.orc_trad_size.argtypes = []
+        L.orc_trad_size.restype = u64
+        if L.orc_trad_size() != ctypes.sizeof(Trad):
+            raise RuntimeError("oracle traditional table layout mismatch")
         L.orc_tables_size.argtypes = []
         L.orc_tables_size.restype = u64
         if L.orc_tables_size() != ctypes.sizeof(Tables):
@@ -105,6 +124,41 @@ def tables(dist, i_max=256, accel=False):
         t.accel = 1 if key[2] else 0
         _tables[key] = t
     return _tables[key]
+
+
+_trad = {}
+
+
+def trad(dist, n=256):
+    """Traditional-ziggurat tables of `dist` with n layers."""
+    key = (dist, n)
+    if key not in _trad:
+        t = Trad()
+        if lib().orc_build_trad(dist, n, ctypes.byref(t)) != 0:
+            raise ValueError("unsupported traditional table %r" % (key,))
+        _trad[key] = t
+    return _trad[key]
+
+
+def trad_arrays(dist, n=256):
+    t = trad(dist, n)
+    return {"n": t.n, "b": t.b, "X": np.array(t.X[:n]), "f": np.array(t.f[:n]), "W": np.array(t.W[:n]),
+            "WS": np.array(t.WS[:n]), "k": np.array(t.k[:n]), "v": t.v, "r": t.r, "invr": t.invr,
+            "hp_r": t.hp_r.decode(), "hp_v": t.hp_v.decode()}
+
+
+def trad_fill(dist, seed, first, n, scale, shift=0.0, threads=1, layers=256, words=False):
+    """FP64 outputs of the traditional sampler (and the slow words used per
+    output if words=True)."""
+    out = np.empty(n, dtype=np.float64)
+    w = np.empty(n, dtype=np.uint32) if words else None
+    ex = ctypes.byref(trad(EXP, layers))
+    nt = ctypes.byref(trad(NORMAL, layers)) if dist == NORMAL else None
+    r = lib().orc_trad_fill(dist, ex, nt, seed, first, n, scale, shift, out.ctypes.data if n else None,
+                            w.ctypes.data if words and n else None, threads)
+    if r != 0:
+        raise ValueError("orc_trad_fill rejected its arguments")
+    return (out, w) if words else out
 
 
 def table_arrays(dist, i_max=256):

@@ -811,6 +811,177 @@ int orc_moments(int dist, int dtype, const orc_tables* ex, const orc_tables* nt,
   return 0;
 }
 
+/* ---- traditional ziggurat ------------------------------------------- */
+
+static hp dens_inverse(int dist, hp y) { return dist == ORC_EXP ? -logq(y) : sqrtq(-2 * logq(y)); }
+
+/* Builds the stack from X_0 = r; returns f_{n-1} - P(0) (the closure
+ * residual, decreasing in r), or +1 if the stack reaches P(0) early. */
+static hp trad_stack(int dist, uint32_t n, hp r, hp* X, hp* f, hp* v_out) {
+  const hp v = r * dens(dist, r) + dens_upper(dist, r);
+  X[0] = r;
+  f[0] = dens(dist, r);
+  for (uint32_t i = 1; i < n; ++i) {
+    f[i] = f[i - 1] + v / X[i - 1];
+    if (i == n - 1) break;
+    if (f[i] >= 1) return 1;
+    X[i] = dens_inverse(dist, f[i]);
+  }
+  *v_out = v;
+  return f[n - 1] - 1;
+}
+
+int orc_build_trad(int dist, uint32_t n, orc_trad* t) {
+  if (dist != ORC_EXP && dist != ORC_NORMAL) return -1;
+  uint32_t b = 0;
+  while ((1u << b) < n) ++b;
+  if ((1u << b) != n || b < 3 || b > 10) return -1;
+  memset(t, 0, sizeof(*t));
+  t->dist = dist;
+  t->n = n;
+  t->b = b;
+  static __thread hp X[ORC_MAX_IMAX + 1], f[ORC_MAX_IMAX + 1];
+  hp lo = 0.5, hi = 40, v = 0;
+  for (int it = 0; it < 2000; ++it) {
+    const hp mid = (lo + hi) / 2;
+    if (mid <= lo || mid >= hi) break;
+    if (trad_stack(dist, n, mid, X, f, &v) > 0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  if (trad_stack(dist, n, hi, X, f, &v) > 0) return -1;
+  X[n - 1] = 0;
+  f[n - 1] = 1;
+  for (uint32_t i = 0; i < n; ++i) {
+    t->X[i] = (double)X[i];
+    t->f[i] = (double)f[i];
+    const hp w = (i == 0) ? v / f[0] : X[i - 1];
+    t->W[i] = (double)w;
+    t->WS[i] = ldexp(t->W[i], -53);
+    t->k[i] = (double)(X[i] / w);
+  }
+  t->v = (double)v;
+  t->r = (double)X[0];
+  t->invr = (double)(1 / X[0]);
+  hpstr(t->hp_r, X[0]);
+  hpstr(t->hp_v, v);
+  return 0;
+}
+
+uint64_t orc_trad_size(void) { return sizeof(orc_trad); }
+
+/* The traditional exponential sampler from a (U1, i) word w: returns x
+ * with the tails nested as X_0 + (X_0 + (... + y)). */
+static double trad_exp_from(const orc_trad* E, uint64_t w, slow_stream* s) {
+  uint32_t nest = 0;
+  double x;
+  for (;;) {
+    const uint32_t i = (uint32_t)(w & (E->n - 1));
+    const uint64_t k = w >> 11;
+    x = (double)k * E->WS[i];
+    if (unif53(k) < E->k[i]) break; /* step 3 */
+    if (i == 0) {                   /* step 4: the tail, by memorylessness */
+      ++nest;
+      w = next_word(s);
+      continue;
+    }
+    const double y = fma(unif53(next_word(s) >> 11), E->f[i] - E->f[i - 1], E->f[i - 1]); /* steps 5-6 */
+    s->tests += 1;
+    if (y < exp(-x)) break;
+    w = next_word(s); /* step 7 */
+  }
+  for (uint32_t c = 0; c < nest; ++c) x = E->r + x;
+  return x;
+}
+
+static double trad_normal_from(const orc_trad* N, const orc_trad* E, uint64_t w, slow_stream* s) {
+  for (;;) {
+    const uint32_t i = (uint32_t)(w & (N->n - 1));
+    const uint64_t k = w >> 11;
+    const double x = (double)k * N->WS[i];
+    if (unif53(k) < N->k[i]) return x;
+    if (i == 0) {
+      for (;;) {
+        const double e1 = trad_exp_from(E, next_word(s), s);
+        const double e2 = trad_exp_from(E, next_word(s), s);
+        const double tt = e1 * N->invr;
+        if (e2 + e2 > tt * tt) return N->r + tt;
+      }
+    }
+    const double y = fma(unif53(next_word(s) >> 11), N->f[i] - N->f[i - 1], N->f[i - 1]);
+    s->tests += 1;
+    if (y < exp(-0.5 * (x * x))) return x;
+    w = next_word(s);
+  }
+}
+
+typedef struct {
+  int dist;
+  const orc_trad *ex, *nt;
+  uint64_t seed, first, lo, hi;
+  double scale, shift;
+  double* out;
+  uint32_t* words;
+} trad_job;
+
+static void* trad_worker(void* arg) {
+  trad_job* jb = (trad_job*)arg;
+  for (uint64_t k = jb->lo; k < jb->hi; ++k) {
+    const uint64_t g = jb->first + k;
+    const uint64_t w = fast_word64(jb->seed, g);
+    slow_stream s;
+    seed_key(jb->seed, s.key);
+    s.n = g;
+    s.t = 0;
+    s.tests = 0;
+    double x;
+    if (jb->dist == ORC_EXP) {
+      x = trad_exp_from(jb->ex, w, &s);
+    } else {
+      x = trad_normal_from(jb->nt, jb->ex, w, &s);
+      if ((w >> 10) & 1) x = -x;
+    }
+    jb->out[k] = fma(jb->scale, x, jb->shift);
+    if (jb->words) jb->words[k] = (uint32_t)s.t;
+  }
+  return NULL;
+}
+
+int orc_trad_fill(int dist, const orc_trad* ex, const orc_trad* nt, uint64_t seed, uint64_t first, uint64_t n,
+                  double scale, double shift, double* out, uint32_t* words, int threads) {
+  if (dist != ORC_EXP && dist != ORC_NORMAL) return -1;
+  if (ex == NULL || ex->dist != ORC_EXP || (dist == ORC_NORMAL && (nt == NULL || nt->dist != ORC_NORMAL)))
+    return -1;
+  if (n > 0 && (out == NULL || first + (n - 1) < first)) return -1;
+  if (threads < 1) threads = 1;
+  if (threads > 256) threads = 256;
+  if ((uint64_t)threads > n) threads = n > 0 ? (int)n : 1;
+  trad_job jobs[256];
+  pthread_t tid[256];
+  for (int k = 0; k < threads; ++k) {
+    trad_job* jb = &jobs[k];
+    jb->dist = dist;
+    jb->ex = ex;
+    jb->nt = nt;
+    jb->seed = seed;
+    jb->first = first;
+    jb->lo = n * (uint64_t)k / (uint64_t)threads;
+    jb->hi = n * (uint64_t)(k + 1) / (uint64_t)threads;
+    jb->scale = scale;
+    jb->shift = shift;
+    jb->out = out;
+    jb->words = words;
+  }
+  if (threads == 1) {
+    trad_worker(&jobs[0]);
+    return 0;
+  }
+  for (int k = 0; k < threads; ++k) pthread_create(&tid[k], NULL, trad_worker, &jobs[k]);
+  for (int k = 0; k < threads; ++k) pthread_join(tid[k], NULL);
+  return 0;
+}
+
 int orc_sample_region(const orc_tables* ex, const orc_tables* nt, int dist, uint32_t j, uint64_t seed, uint64_t index0,
                       uint64_t n, double* out) {
   const orc_tables* t = (dist == ORC_EXP) ? ex : nt;

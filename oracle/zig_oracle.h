@@ -119,6 +119,39 @@ int orc_sample_region(const orc_tables* ex, const orc_tables* nt, int dist, uint
 /* The alias draw j(r) for a 64-bit word r. */
 uint32_t orc_alias_draw(const orc_tables* t, uint64_t r);
 
+/* ---- traditional ziggurat (Table 1, right column), for the A/B test --
+ * n layers of equal area v covering P: layer 0 is the rectangle
+ * [0, X_0] x [0, f_0] plus the tail beyond X_0 (width W_0 = v / f_0),
+ * layer i >= 1 the rectangle [0, X_{i-1}] x [f_{i-1}, f_i] (width
+ * W_i = X_{i-1}), with f_i = P(X_i) and X_{n-1} = 0, f_{n-1} = P(0) = 1;
+ * X_0 = r is solved so that the stack closes at the top.  k_i = X_i / W_i
+ * is the fraction of layer i that lies wholly under P. */
+typedef struct {
+  int dist;
+  uint32_t n, b;
+  double X[ORC_MAX_IMAX + 1];
+  double f[ORC_MAX_IMAX + 1];
+  double W[ORC_MAX_IMAX];
+  double WS[ORC_MAX_IMAX];  /* W_i * 2^-53 */
+  double k[ORC_MAX_IMAX];
+  double v, r, invr;
+  char hp_r[48], hp_v[48];
+} orc_trad;
+
+int orc_build_trad(int dist, uint32_t n, orc_trad* t);
+
+/* FP64 fill with the traditional sampler on the same uniform streams as
+ * the modified one: output g takes its first (U1, i) from its fast word
+ * (index bits 0..b-1, normal sign bit 10, U1 from bits 11..63); a layer's
+ * wedge test draws U2, and every restart a new (U1, i), from the output's
+ * slow stream, as do the tails (exponential: X_0 plus a fresh traditional
+ * exponential; normal: Marsaglia's method on two traditional
+ * exponentials).  `words` (may be NULL) receives the slow words used per
+ * output. */
+int orc_trad_fill(int dist, const orc_trad* ex, const orc_trad* nt, uint64_t seed, uint64_t first, uint64_t n,
+                  double scale, double shift, double* out, uint32_t* words, int threads);
+uint64_t orc_trad_size(void);
+
 /* Size of orc_tables, so that foreign callers can allocate it. */
 uint64_t orc_tables_size(void);
 
