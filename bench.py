@@ -288,6 +288,34 @@ def moments_bench(torch, zig):
     return out
 
 
+def traditional_ab(torch, zig):
+    """The comparison of Table 1 on this GPU: the modified sampler and the
+    traditional ziggurat on the headline fills (2^30 FP64, same streams,
+    same tile/compaction/store kernel structure), each at its default
+    shape and the traditional one also at its best of a few shapes."""
+    out = torch.empty(N_C3, dtype=torch.float64, device="cuda")
+    res = {}
+    shapes = [(0, 0), (256, 8), (512, 4), (512, 2), (1024, 2), (512, 1)]
+    for dist, name, seed, p0, p1 in [(0, "exp", 11, 2.5, 0.0), (1, "normal", 12, -1.0, 3.0)]:
+        _, dd = timed_fills(torch, zig, [(lambda: zig.fill(out, dist, seed, 0, p0, p1), N_C3 * 8)], 10, 3)
+        mod_ms = float(np.mean(dd))
+        trad = {}
+        for wg, spl in shapes:
+            lt = zig.Launch(0, wg, spl, zig.LAUNCH_TRADITIONAL)
+            _, dd = timed_fills(torch, zig, [(lambda: zig.fill(out, dist, seed, 0, p0, p1, launch=lt), N_C3 * 8)],
+                                10, 3)
+            trad["default" if wg == 0 else "%dx%d" % (wg, spl)] = round(float(np.mean(dd)), 4)
+        best = min(trad, key=trad.get)
+        mt = zig.zig_get_tables(dist, 256)
+        tt = zig.zig_get_trad_tables(dist, 256)
+        res[name] = {"modified_ms": round(mod_ms, 4), "traditional_ms": trad, "traditional_best": best,
+                     "traditional_over_modified": round(trad[best] / mod_ms, 4),
+                     "quick_exit": {"modified": mt["L"] / 256.0, "traditional": round(float(tt["k"].mean()), 5)}}
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
 def autotune_report(zig):
     """Runs the autotuner on this device (cache in a temporary file) and
     reports, per (dist, dtype, size class), the chosen shape and its time
@@ -442,6 +470,9 @@ def main():
         log("fused generate-and-reduce")
         result["moments"] = moments_bench(torch, zig)
         log("moments: %s" % json.dumps(result["moments"]))
+        log("modified vs traditional ziggurat")
+        result["traditional_ab"] = traditional_ab(torch, zig)
+        log("traditional_ab: %s" % json.dumps(result["traditional_ab"]))
         log("autotuner")
         result["autotune"] = autotune_report(zig)
         log("autotune: %s" % json.dumps(result["autotune"]))

@@ -105,6 +105,31 @@ typedef struct {
 } zig_table_view;
 int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out);
 
+/* Host-side view of the traditional ziggurat's tables (the comparison
+ * sampler of Table 1), n = i_max layers of equal area v, built in
+ * binary128 and rounded to double.  Layer 0 is the rectangle
+ * [0, X_0] x [0, f_0] plus the tail beyond X_0 = r; layer i >= 1 is
+ * [0, X_{i-1}] x [f_{i-1}, f_i]; X_{n-1} = 0, f_{n-1} = 1; r is fixed by
+ * the top layer having area v too.  All arrays have n entries:
+ *   X, f   layer corners (f_i = P(X_i))
+ *   W      layer widths: W_0 = v / f_0, W_i = X_{i-1}
+ *   WS     W_i * 2^-53
+ *   k      X_i / W_i, the share of layer i wholly under the density
+ *   KQ     ceil(2^53 k_i): magnitude bits below it quick-accept
+ * Pointers stay valid until the process ends.  Errors: ZIG_EINVAL,
+ * ZIG_ENOTABLES. */
+typedef struct {
+  uint32_t dist, n, b, pad;
+  const double* X;
+  const double* f;
+  const double* W;
+  const double* WS;
+  const double* k;
+  const uint64_t* KQ;
+  double r, v, invr;
+} zig_trad_view;
+int zig_get_trad_tables(uint32_t dist, uint32_t i_max, zig_trad_view* out);
+
 /* out[k] = sample of Exp(lambda) at global index first_index + k, k < n:
  * x from the modified ziggurat for e^-x (Table 1; tail by recursion on
  * the memoryless tail; overhangs by the reflected three-region test of
@@ -140,8 +165,22 @@ int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dt
  * evaluating it; the box containing x = 1 keeps plain rejection.  Its
  * outputs are a different exact sample than the default's (the slow
  * outputs differ; fast-path and tail outputs are the same); the
- * exponential ignores the flag. */
+ * exponential ignores the flag.
+ * ZIG_LAUNCH_TRADITIONAL replaces the modified sampler with the
+ * traditional ziggurat the paper compares against (Table 1, right
+ * column; Marsaglia & Tsang's stack of i_max equal-area layers, tables as
+ * zig_get_trad_tables describes): output g takes layer i and magnitude
+ * bits k from its fast word exactly as the modified sampler does and
+ * returns x = k W_i 2^-53 when k < KQ[i]; otherwise a wedge test draws
+ * U2 from the output's slow stream (accept when
+ * f_{i-1} + U2 (f_i - f_{i-1}) < P(x)), and each rejection takes a fresh
+ * (i, k) word from the same stream; layer 0 past X_0 is the tail
+ * (exponential: X_0 plus a fresh traditional exponential; normal:
+ * Marsaglia's method on two traditional exponentials).  FP64 only, no
+ * trace; not combinable with ZIG_LAUNCH_NORMAL_ACCEL.  It exists for the
+ * comparison of Table 1. */
 #define ZIG_LAUNCH_NORMAL_ACCEL 1u /* normal overhangs: the accelerated variant (see below) */
+#define ZIG_LAUNCH_TRADITIONAL 2u  /* the traditional ziggurat, for comparison */
 typedef struct {
   uint32_t i_max;
   uint32_t wg;

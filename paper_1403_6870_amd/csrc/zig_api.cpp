@@ -107,6 +107,72 @@ int device_tables(uint32_t i_max, const DevTable** out) {
   return ZIG_OK;
 }
 
+// Traditional sampler tables (the comparison of Table 1), host and device,
+// built on first use like the modified ones.
+struct TradPair {
+  HostTrad t[2];
+};
+std::map<uint32_t, std::unique_ptr<TradPair>> g_thost;  // by i_max
+std::map<std::pair<int, uint32_t>, DevTrad*> g_tdev;     // (device, i_max) -> [exp, normal]
+
+int host_trad_locked(uint32_t i_max, TradPair** out) {
+  auto it = g_thost.find(i_max);
+  if (it != g_thost.end()) {
+    *out = it->second.get();
+    return ZIG_OK;
+  }
+  std::unique_ptr<TradPair> tp(new TradPair());
+  for (uint32_t d = 0; d < 2; ++d) {
+    std::string err = build_host_trad(d, i_max, &tp->t[d]);
+    if (!err.empty()) return fail(ZIG_ENOTABLES, "traditional tables: " + err);
+  }
+  *out = tp.get();
+  g_thost[i_max] = std::move(tp);
+  return ZIG_OK;
+}
+
+int device_trad(uint32_t i_max, const DevTrad** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, i_max);
+  auto it = g_tdev.find(key);
+  if (it != g_tdev.end()) {
+    *out = it->second;
+    return ZIG_OK;
+  }
+  TradPair* tp = nullptr;
+  int r = host_trad_locked(i_max, &tp);
+  if (r != ZIG_OK) return r;
+  DevTrad host[2];
+  std::memset(host, 0, sizeof(host));
+  for (uint32_t d = 0; d < 2; ++d) {
+    const HostTrad& h = tp->t[d];
+    host[d].dist = h.dist;
+    host[d].n = h.n;
+    host[d].b = h.b;
+    host[d].r = h.r;
+    host[d].invr = h.invr;
+    for (uint32_t i = 0; i < h.n; ++i) {
+      host[d].WS[i] = h.WS[i];
+      host[d].KQ[i] = h.KQ[i];
+      host[d].f[i] = h.f[i];
+    }
+  }
+  DevTrad* d = nullptr;
+  e = hipMalloc(&d, sizeof(host));
+  if (e != hipSuccess) return fail(ZIG_ENOMEM, std::string("hipMalloc(tables): ") + hipGetErrorString(e));
+  e = hipMemcpy(d, host, sizeof(host), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return fail(ZIG_EHIP, std::string("hipMemcpy(tables): ") + hipGetErrorString(e));
+  }
+  g_tdev[key] = d;
+  *out = d;
+  return ZIG_OK;
+}
+
 // Tile counters of the persistent fill kernel, one pair per (device,
 // stream): launches on one stream run in order and each leaves its pair at
 // zero, so a stream can reuse its pair without any reset work.
@@ -192,7 +258,15 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   if (launch) cfg = *launch;
   const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
   if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
-  if (cfg.flags & ~ZIG_LAUNCH_NORMAL_ACCEL) return fail(ZIG_EINVAL, "unknown launch flags");
+  if (cfg.flags & ~(ZIG_LAUNCH_NORMAL_ACCEL | ZIG_LAUNCH_TRADITIONAL))
+    return fail(ZIG_EINVAL, "unknown launch flags");
+  const bool trad = (cfg.flags & ZIG_LAUNCH_TRADITIONAL) != 0;
+  if (trad) {
+    if (cfg.flags & ZIG_LAUNCH_NORMAL_ACCEL)
+      return fail(ZIG_EINVAL, "ZIG_LAUNCH_TRADITIONAL does not combine with ZIG_LAUNCH_NORMAL_ACCEL");
+    if (dtype != kF64) return fail(ZIG_EINVAL, "the traditional sampler is FP64 only");
+    if (trace) return fail(ZIG_EINVAL, "the traditional sampler has no trace");
+  }
   if (n == 0) return ZIG_OK;
   if (out == nullptr) return fail(ZIG_EINVAL, "out is null");
   const uint64_t esize = dtype == kF64 ? 8 : 4;
@@ -214,6 +288,11 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   const DevTable* tabs = nullptr;
   r = device_tables(i_max, &tabs);
   if (r != ZIG_OK) return r;
+  const DevTrad* ttabs = nullptr;
+  if (trad) {
+    r = device_trad(i_max, &ttabs);
+    if (r != ZIG_OK) return r;
+  }
 
   const uint64_t per_block = dtype == kF64 ? 2 : 4;
   const uint64_t last = first + (n - 1);
@@ -234,6 +313,10 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   a.t_region = t_region;
   a.t_words = t_words;
   a.t_tests = t_tests;
+  if (trad) {
+    a.ttab = ttabs + dist;
+    a.tetab = ttabs + kDistExp;
+  }
 
   r = stream_counters(stream, &a.counters);
   if (r != ZIG_OK) return r;
@@ -256,7 +339,8 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
     a.blk0 = blk0 + start * tile;
     a.tiles = (uint32_t)((tiles - start < chunk) ? tiles - start : chunk);
     a.chunk = sh.chunk;
-    int e = launch_fill(dist, dtype, sh.wg, sh.spl, trace, a, stream);
+    int e = trad ? launch_trad(dist, sh.wg, sh.spl, a, stream)
+                 : launch_fill(dist, dtype, sh.wg, sh.spl, trace, a, stream);
     if (e != 0)
       return fail(ZIG_EHIP, std::string("fill launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
   }
@@ -321,6 +405,32 @@ int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out) {
   return ZIG_OK;
 }
 
+int zig_get_trad_tables(uint32_t dist, uint32_t i_max, zig_trad_view* out) {
+  zig::g_error.clear();
+  if (out == nullptr) return zig::fail(ZIG_EINVAL, "out is null");
+  if (dist > 1) return zig::fail(ZIG_EINVAL, "unknown distribution");
+  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  std::lock_guard<std::mutex> lk(zig::g_mu);
+  zig::TradPair* tp = nullptr;
+  int r = zig::host_trad_locked(i_max, &tp);
+  if (r != ZIG_OK) return r;
+  const zig::HostTrad& t = tp->t[dist];
+  out->dist = t.dist;
+  out->n = t.n;
+  out->b = t.b;
+  out->pad = 0;
+  out->X = t.X.data();
+  out->f = t.f.data();
+  out->W = t.W.data();
+  out->WS = t.WS.data();
+  out->k = t.k.data();
+  out->KQ = t.KQ.data();
+  out->r = t.r;
+  out->v = t.v;
+  out->invr = t.invr;
+  return ZIG_OK;
+}
+
 int zig_fill(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
              void* out, void* stream, const zig_launch* launch) {
   return zig::fill_impl(dist, dtype, seed, first_index, n, p0, p1, out, stream, launch, false, nullptr, nullptr,
@@ -358,6 +468,8 @@ int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_ind
   if (launch) cfg = *launch;
   const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
   if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (cfg.flags & ZIG_LAUNCH_TRADITIONAL)
+    return zig::fail(ZIG_EINVAL, "the moments kernel runs the modified sampler only");
   if (cfg.flags & ~ZIG_LAUNCH_NORMAL_ACCEL) return zig::fail(ZIG_EINVAL, "unknown launch flags");
   if ((cfg.wg && cfg.wg != 256) || (cfg.spl && cfg.spl != 8))
     return zig::fail(ZIG_EINVAL, "the moments kernel runs 256 lanes x 8 blocks (its summation order)");

@@ -133,6 +133,8 @@ __global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
       a.t_region = nullptr;
       a.t_words = nullptr;
       a.t_tests = nullptr;
+      a.ttab = nullptr;
+      a.tetab = nullptr;
       FillCtx c;
       c.ex = vexp;
       c.k0 = (uint32_t)q.seed;

@@ -265,6 +265,107 @@ __device__ __forceinline__ bool normal_sign(uint64_t g, uint32_t k0, uint32_t k1
   }
 }
 
+// ---- the traditional ziggurat (Table 1, right column), for comparison --
+
+// Its tables as the slow path reads them: layer widths W_i 2^-53, the
+// quick-accept thresholds on the 53 magnitude bits, the layer heights.
+struct TradView {
+  const double* WS;
+  const uint64_t* KQ;
+  const double* f;
+  uint32_t imask;
+  double r, invr;
+};
+
+__device__ __forceinline__ TradView trad_view(const DevTrad* t) {
+  TradView v;
+  v.WS = t->WS;
+  v.KQ = t->KQ;
+  v.f = t->f;
+  v.imask = t->n - 1;
+  v.r = t->r;
+  v.invr = t->invr;
+  return v;
+}
+
+// Traditional exponential from the word w: layer i from its low bits, the
+// 53 magnitude bits k from bits 11..63, x = k W_i 2^-53.  Quick accept when
+// k < KQ[i]; layer 0 beyond X_0 is the tail, X_0 plus a fresh traditional
+// exponential (nesting added innermost first); any other layer tests
+// f_{i-1} + U2 (f_i - f_{i-1}) < e^-x with U2 from the slow stream and on
+// rejection starts over from a fresh word.
+__device__ __forceinline__ double trad_exp(const TradView& E, uint64_t w, SlowStream& s, uint32_t& tests) {
+  uint32_t nest = 0;
+  double x;
+  for (;;) {
+    const uint32_t i = (uint32_t)w & E.imask;
+    const uint64_t k = w >> 11;
+    x = (double)k * E.WS[i];
+    if (k < E.KQ[i]) break;
+    if (i == 0) {
+      ++nest;
+      w = s.next();
+      continue;
+    }
+    const double lo = E.f[i - 1];
+    const double y = __builtin_fma(lattice53(s.next() >> 11), E.f[i] - lo, lo);
+    ++tests;
+    if (y < exp(-x)) break;
+    w = s.next();
+  }
+  for (uint32_t c = 0; c < nest; ++c) x = E.r + x;
+  return x;
+}
+
+// Traditional normal magnitude from the word w; the tail beyond X_0 = r
+// uses Marsaglia's method on two traditional exponentials.
+__device__ __forceinline__ double trad_normal(const TradView& N, const TradView& E, uint64_t w, SlowStream& s,
+                                              uint32_t& tests) {
+  for (;;) {
+    const uint32_t i = (uint32_t)w & N.imask;
+    const uint64_t k = w >> 11;
+    const double x = (double)k * N.WS[i];
+    if (k < N.KQ[i]) return x;
+    if (i == 0) {
+      for (;;) {
+        const double e1 = trad_exp(E, s.next(), s, tests);
+        const double e2 = trad_exp(E, s.next(), s, tests);
+        const double t = e1 * N.invr;
+        if (e2 + e2 > t * t) return N.r + t;
+      }
+    }
+    const double lo = N.f[i - 1];
+    const double y = __builtin_fma(lattice53(s.next() >> 11), N.f[i] - lo, lo);
+    ++tests;
+    if (y < exp(-0.5 * (x * x))) return x;
+    w = s.next();
+  }
+}
+
+// Output g (FP64) of the traditional sampler after its first word missed
+// the quick test: the word is recomputed from the fast block (it also
+// holds the normal sign, bit 10) and the sampler runs from it.
+template <uint32_t DIST>
+__device__ __forceinline__ double trad_slow(const TradView& own, const TradView& ex, uint64_t g, uint32_t k0,
+                                            uint32_t k1, bool& neg, uint32_t& words, uint32_t& tests) {
+  const uint64_t m = g >> 1;
+  uint32_t c0 = (uint32_t)m, c1 = (uint32_t)(m >> 32), c2 = 0u, c3 = 0u;
+  philox10(c0, c1, c2, c3, k0, k1);
+  const uint64_t w = (g & 1) ? ((uint64_t)c2 | ((uint64_t)c3 << 32)) : ((uint64_t)c0 | ((uint64_t)c1 << 32));
+  SlowStream s(g, k0, k1);
+  tests = 0;
+  double x;
+  if constexpr (DIST == kDistExp) {
+    neg = false;
+    x = trad_exp(own, w, s, tests);
+  } else {
+    neg = (w >> 10) & 1u;
+    x = trad_normal(own, ex, w, s, tests);
+  }
+  words = s.t;
+  return x;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }

@@ -1,4 +1,5 @@
-// The fill kernel of the modified ziggurat sampler for gfx950.
+// The fill kernel of the modified ziggurat sampler for gfx950 (and, for
+// the comparison of Table 1, of the traditional one; see fill_tile).
 //
 // Work is cut into tiles of WG * S consecutive Philox blocks (2 FP64 or 4
 // FP32 outputs per block), each written contiguously by one workgroup.  A
@@ -20,6 +21,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "zig_device.hpp"
@@ -72,6 +76,7 @@ struct FillLds {
 // the Philox key and the location-scale pair.
 struct FillCtx {
   dev::TabView own, ex;
+  dev::TradView tr, trex;  // the traditional sampler's tables (own in LDS)
   const void* fast;
   uint32_t k0, k1;
   double scale, shift;
@@ -117,6 +122,31 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
   return c;
 }
 
+// The traditional sampler's context (FP64): widths W_i 2^-53 in the fast
+// table, quick-accept thresholds and layer heights in LDS, the exponential
+// tables of the normal tail read from device memory.
+template <uint32_t DIST, int WG, int S>
+__device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a, FillLds<kF64, WG, S>& sh) {
+  const DevTrad* tb = a.ttab;
+  for (uint32_t i = threadIdx.x; i < kMaxLayers; i += WG) {
+    sh.xs[i] = tb->WS[i];
+    sh.T[i] = tb->KQ[i];
+    sh.f[i] = tb->f[i];
+  }
+  FillCtx c = {};
+  c.tr = dev::trad_view(tb);
+  c.tr.WS = sh.xs;
+  c.tr.KQ = sh.T;
+  c.tr.f = sh.f;
+  c.trex = dev::trad_view(a.tetab);
+  c.fast = sh.xs;
+  c.k0 = (uint32_t)a.seed;
+  c.k1 = (uint32_t)(a.seed >> 32);
+  c.scale = a.scale;
+  c.shift = a.shift;
+  return c;
+}
+
 // One tile (tile index t of this launch).  Ends with the staging tile
 // written out; callers separate consecutive tiles with a barrier.
 //
@@ -124,7 +154,12 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
 // (S1..S5 into msum[0..4]) in the fixed order of the moments definition:
 // lane l adds the outputs of its blocks l + WG * s in order of s, then the
 // lane sums are reduced by halving.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool MOM = false, bool ACCEL = false>
+//
+// With TRAD set (FP64 only) the sampler is the traditional ziggurat: the
+// fast word quick-accepts when its magnitude bits lie below the layer's
+// threshold, and phase B runs the traditional slow path from that word.
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool MOM = false, bool ACCEL = false,
+          bool TRAD = false>
 __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t,
                                           double* msum = nullptr) {
   using Sh = FillShape<DT, WG, S>;
@@ -134,12 +169,13 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   constexpr int NWAVE = Sh::NWAVE;
   constexpr int NWORD = Sh::NWORD;
   constexpr int TILE = Sh::TILE;
+  static_assert(!TRAD || (DT == kF64 && !TRACE && !MOM && !ACCEL), "traditional sampler: plain FP64 fills");
 
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
   const uint32_t wave = tid >> 6;
-  const uint32_t L = c.own.L;
-  const uint32_t imask = c.own.imask;
+  const uint32_t L = TRAD ? 0u : c.own.L;
+  const uint32_t imask = TRAD ? c.tr.imask : c.own.imask;
   const float fscale = (float)c.scale, fshift = (float)c.shift;
   OutT* const out = static_cast<OutT*>(a.out);
   VecT* const stage = static_cast<VecT*>(sh.stage);
@@ -165,17 +201,23 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
         if constexpr (!IN) live = (m <= a.blk_last) && (g >= a.first) && (g <= a.last);
         uint32_t i;
         OutT x;
+        bool miss;  // the fast word does not decide the output
         if constexpr (DT == kF64) {
           const uint64_t w =
               (o == 0) ? ((uint64_t)c0 | ((uint64_t)c1 << 32)) : ((uint64_t)c2 | ((uint64_t)c3 << 32));
           i = (uint32_t)w & imask;
           x = (double)(w >> 11) * xs[i];
+          if constexpr (TRAD)
+            miss = (w >> 11) >= c.tr.KQ[i];
+          else
+            miss = i >= L;
           if constexpr (DIST == kDistNormal) {
             if ((w >> 10) & 1u) x = -x;
           }
         } else {
           const uint32_t w = (o == 0) ? c0 : (o == 1) ? c1 : (o == 2) ? c2 : c3;
           i = w & imask;
+          miss = i >= L;
           if constexpr (DIST == kDistExp) {
             x = (float)(w >> 8) * xs[i];
           } else {
@@ -186,7 +228,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
         // a slow output's value here is a placeholder that phase B replaces;
         // for the exponential the shift is +0 and x >= 0, where
         // fma(scale, x, +0) is the rounded product
-        const bool slow = live && (i >= L);
+        const bool slow = live && miss;
         if constexpr (DIST == kDistExp) {
           if constexpr (DT == kF64)
             v[o] = c.scale * x;
@@ -279,10 +321,15 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
     const uint64_t g = (tile0 + blk) * O + o;
     OutT* place = stage_s + blk * O + o;
     bool neg = false;
-    if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, c.k0, c.k1);
-    int32_t region;
+    int32_t region = -1;
     uint32_t words, tests;
-    const double mag = dev::slow_magnitude<DIST, ACCEL>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
+    double mag;
+    if constexpr (TRAD) {
+      mag = dev::trad_slow<DIST>(c.tr, c.trex, g, c.k0, c.k1, neg, words, tests);
+    } else {
+      if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, c.k0, c.k1);
+      mag = dev::slow_magnitude<DIST, ACCEL>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
+    }
     OutT x = (OutT)mag;
     if (neg) x = -x;
     if constexpr (DIST == kDistExp) {
@@ -387,10 +434,15 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
 // device on that address), so the tiles in flight stay a window that
 // sweeps through the output in address order.  The last workgroup to leave
 // resets the counters for the next launch on the same stream.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false>
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false>
 __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
   __shared__ FillLds<DT, WG, S> sh;
-  const FillCtx c = load_tables<DIST, DT, WG, S>(a, sh);
+  const FillCtx c = [&] {
+    if constexpr (TRAD)
+      return load_trad_tables<DIST, WG, S>(a, sh);
+    else
+      return load_tables<DIST, DT, WG, S>(a, sh);
+  }();
   TileLds tl;
   tl.stage = sh.stage;
   tl.slowmap = sh.slowmap;
@@ -402,7 +454,7 @@ __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
     if (t0 >= a.tiles) break;
     const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
     for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, WG, S, TRACE, false, ACCEL>(a, c, tl, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE, false, ACCEL, TRAD>(a, c, tl, (uint32_t)t);
       __syncthreads();
     }
   }
@@ -412,6 +464,53 @@ __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
       atomicExch(&a.counters[1], 0u);
     }
   }
+}
+
+// Workgroups of one kernel variant resident on the whole device.
+template <class K>
+int resident_groups(K kernel, int wg, size_t lds, int* out) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, size_t, int>, int> cache;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  const auto key = std::make_tuple((const void*)kernel, wg, lds, dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    *out = it->second;
+    return 0;
+  }
+  int per_cu = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, wg, lds);
+  if (e != hipSuccess) return (int)e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return (int)e;
+  if (per_cu < 1) return (int)hipErrorInvalidConfiguration;
+  *out = per_cu * cus;
+  cache[key] = *out;
+  return 0;
+}
+
+// Launch of one fill-kernel variant: as many persistent workgroups as are
+// resident on the device, fewer when the launch has fewer counter steps.
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false>
+int launch_one(const FillArgs& args, hipStream_t st) {
+  auto kernel = fill_kernel<DIST, DT, WG, S, TRACE, ACCEL, TRAD>;
+  int groups = 0;
+  int e = resident_groups(kernel, WG, 0, &groups);
+  if (e != 0) return e;
+  FillArgs a = args;
+  // tiles per counter step: as asked, but small enough that every resident
+  // workgroup gets a couple of steps
+  uint64_t chunk = a.tiles / (2ull * (uint64_t)groups);
+  if (chunk > a.chunk) chunk = a.chunk;
+  if (chunk < 1) chunk = 1;
+  a.chunk = (uint32_t)chunk;
+  const uint64_t steps = (a.tiles + chunk - 1) / chunk;
+  const uint32_t grid = steps < (uint64_t)groups ? (uint32_t)steps : (uint32_t)groups;
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(WG), 0, st, a);
+  return (int)hipGetLastError();
 }
 
 }  // namespace zig

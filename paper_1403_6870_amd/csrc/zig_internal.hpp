@@ -51,6 +51,32 @@ struct HostTable {
 // Returns an empty string on success, else a message.
 std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out);
 
+// Tables of the traditional ziggurat (Marsaglia & Tsang), the comparison
+// sampler of Table 1, as the kernels read them: n layers of equal area v;
+// layer 0 is the rectangle [0, X_0] x [0, f_0] plus the tail beyond X_0
+// (width W_0 = v / f_0), layer i >= 1 the rectangle [0, X_{i-1}] x
+// [f_{i-1}, f_i] (width W_i = X_{i-1}); X_{n-1} = 0 and f_{n-1} = 1.  A draw
+// with magnitude bits k (53 bits) in layer i has x = k W_i 2^-53 and lies
+// wholly under the density when k < KQ[i] = ceil(2^53 X_i / W_i).
+struct DevTrad {
+  uint32_t dist, n, b, pad;
+  double r, invr;
+  double WS[kMaxLayers];
+  uint64_t KQ[kMaxLayers];
+  double f[kMaxLayers];
+};
+static_assert(sizeof(DevTrad) == 6176, "DevTrad layout");
+
+struct HostTrad {
+  uint32_t dist = 0, n = 0, b = 0;
+  std::vector<double> X, f, W, WS, k;
+  std::vector<uint64_t> KQ;
+  double r = 0.0, v = 0.0, invr = 0.0;
+};
+
+// Builds the traditional stack of n layers in binary128 (zig_tables.cpp).
+std::string build_host_trad(uint32_t dist, uint32_t n, HostTrad* out);
+
 // Kernel-side argument block of a plain fill.
 struct FillArgs {
   uint64_t seed;
@@ -75,6 +101,9 @@ struct FillArgs {
   int32_t* t_region;
   uint32_t* t_words;
   uint32_t* t_tests;
+  // traditional sampler only: its tables (distribution, exponential)
+  const DevTrad* ttab;
+  const DevTrad* tetab;
 };
 
 // Launch of one (dist, dtype, wg, spl) variant over a.tiles tiles, with as
@@ -82,6 +111,10 @@ struct FillArgs {
 // Returns 0 or a hipError_t value.
 int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, const FillArgs& a,
                 void* stream);
+
+// The same for the traditional sampler, FP64 only (zig_trad.hip); a.ttab
+// and a.tetab set.
+int launch_trad(uint32_t dist, uint32_t wg, uint32_t spl, const FillArgs& a, void* stream);
 
 // Raw moments (zig_moments.hip): one segment of at most kMomSegTiles tiles
 // of 2048 blocks (a.tiles, a.blk0 set by the caller); tile_sums holds

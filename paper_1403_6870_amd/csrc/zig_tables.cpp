@@ -257,4 +257,75 @@ std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out) {
   return std::string();
 }
 
+// Traditional stack of n layers (Marsaglia & Tsang; the right column of
+// Table 1).  Given the base X_0 = r, every layer has the area
+// v = r P(r) + (mass beyond r); layer i >= 1 sits on f_{i-1} with width
+// X_{i-1}, so f_i = f_{i-1} + v / X_{i-1} and X_i = P^{-1}(f_i).  The right r
+// leaves for the top layer, of width X_{n-2} and height 1 - f_{n-2}, exactly
+// the area v: a larger r leaves it too much, a smaller one too little (or
+// the stack reaches P(0) = 1 early).  r is found by bisection down to
+// adjacent binary128 values.
+std::string build_host_trad(uint32_t dist, uint32_t n, HostTrad* out) {
+  if (dist != kDistExp && dist != kDistNormal) return "unknown distribution";
+  uint32_t b = 0;
+  while (b < 31 && (1u << b) < n) ++b;
+  if ((1u << b) != n || n < 8 || n > kMaxLayers) return "i_max must be a power of two in [8, 256]";
+  const Density P{dist};
+  auto inverse = [&](q128 y) { return dist == kDistExp ? -logq(y) : sqrtq(-2 * logq(y)); };
+  std::vector<q128> X(n), f(n);
+  q128 v = 0;
+  // +1: r too large (top layer too big); -1: r too small
+  auto side = [&](q128 r) -> int {
+    v = r * P.p(r) + P.upper(r);
+    X[0] = r;
+    f[0] = P.p(r);
+    for (uint32_t i = 1; i + 1 < n; ++i) {
+      f[i] = f[i - 1] + v / X[i - 1];
+      if (f[i] >= 1) return -1;
+      X[i] = inverse(f[i]);
+    }
+    return X[n - 2] * (1 - f[n - 2]) > v ? 1 : -1;
+  };
+  q128 small = 0.25Q, large = 64;
+  if (side(small) != -1 || side(large) != 1) return "traditional stack: no bracket";
+  for (;;) {
+    const q128 mid = 0.5Q * (small + large);
+    if (!(mid > small && mid < large)) break;
+    if (side(mid) > 0)
+      large = mid;
+    else
+      small = mid;
+  }
+  if (side(large) != 1) return "traditional stack: bisection failed";
+  X[n - 1] = 0;
+  f[n - 1] = 1;
+
+  HostTrad& t = *out;
+  t = HostTrad();
+  t.dist = dist;
+  t.n = n;
+  t.b = b;
+  t.X.resize(n);
+  t.f.resize(n);
+  t.W.resize(n);
+  t.WS.resize(n);
+  t.k.resize(n);
+  t.KQ.resize(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const q128 w = i == 0 ? v / f[0] : X[i - 1];
+    t.X[i] = (double)X[i];
+    t.f[i] = (double)f[i];
+    t.W[i] = (double)w;
+    t.WS[i] = std::ldexp(t.W[i], -53);
+    t.k[i] = (double)(X[i] / w);
+    // k U1 < k_i for the 53-bit lattice value U1 = k 2^-53 exactly when the
+    // integer k is below ceil(2^53 k_i)
+    t.KQ[i] = (uint64_t)std::ceil(std::ldexp(t.k[i], 53));
+  }
+  t.r = t.X[0];
+  t.v = (double)v;
+  t.invr = (double)(1 / X[0]);
+  return std::string();
+}
+
 }  // namespace zig

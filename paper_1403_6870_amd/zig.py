@@ -42,11 +42,19 @@ class TableView(ctypes.Structure):
                 ("eps_cvx", dbl), ("del_ccv", dbl), ("K_cvx", u64), ("K_ccv", u64)]
 
 
+class TradView(ctypes.Structure):
+    _fields_ = [("dist", u32), ("n", u32), ("b", u32), ("pad", u32),
+                ("X", ctypes.POINTER(dbl)), ("f", ctypes.POINTER(dbl)), ("W", ctypes.POINTER(dbl)),
+                ("WS", ctypes.POINTER(dbl)), ("k", ctypes.POINTER(dbl)), ("KQ", ctypes.POINTER(u64)),
+                ("r", dbl), ("v", dbl), ("invr", dbl)]
+
+
 class Launch(ctypes.Structure):
     _fields_ = [("i_max", u32), ("wg", u32), ("spl", u32), ("flags", u32)]
 
 
 LAUNCH_NORMAL_ACCEL = 1
+LAUNCH_TRADITIONAL = 2
 
 
 class Request(ctypes.Structure):
@@ -114,6 +122,7 @@ def _sig(name, res, args):
 
 _build = _sig("zig_build_tables", i32, [u32])
 _get = _sig("zig_get_tables", i32, [u32, u32, ctypes.POINTER(TableView)])
+_get_trad = _sig("zig_get_trad_tables", i32, [u32, u32, ctypes.POINTER(TradView)])
 _fill_exp = _sig("zig_fill_exp", i32, [u64, u64, u64, u32, dbl, vp, vp])
 _fill_normal = _sig("zig_fill_normal", i32, [u64, u64, u64, u32, dbl, dbl, vp, vp])
 _fill = _sig("zig_fill", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, ctypes.POINTER(Launch)])
@@ -143,7 +152,7 @@ _moments = _sig("zig_moments", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, 
 _last_error = _sig("zig_last_error", ctypes.c_char_p, [])
 _version = _sig("zig_version", ctypes.c_char_p, [])
 
-EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
+EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_get_trad_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
            "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_moments", "zig_autotune", "zig_tuned_shape",
            "zig_tuned_batch_shape", "zig_autotune_reset", "zig_server_now_ns", "zig_server_create",
            "zig_server_submit", "zig_server_wait", "zig_server_release", "zig_server_drop_client",
@@ -190,6 +199,19 @@ def zig_get_tables(dist, i_max=256):
         "q": arr(v.q, L + 1, np.uint64), "T": arr(v.T, im, np.uint64), "A": arr(v.alias, im, np.uint32),
         "eps": v.eps, "K_eps": int(v.K_eps), "X0": v.X0, "invX0": v.invX0,
         "eps_cvx": v.eps_cvx, "del_ccv": v.del_ccv, "K_cvx": int(v.K_cvx), "K_ccv": int(v.K_ccv),
+    }
+
+
+def zig_get_trad_tables(dist, i_max=256):
+    v = TradView()
+    _check(_get_trad(dist, i_max, ctypes.byref(v)))
+    n = v.n
+    arr = lambda p, dt: np.ctypeslib.as_array(p, shape=(n,)).astype(dt).copy()
+    return {
+        "dist": v.dist, "n": n, "b": v.b,
+        "X": arr(v.X, np.float64), "f": arr(v.f, np.float64), "W": arr(v.W, np.float64),
+        "WS": arr(v.WS, np.float64), "k": arr(v.k, np.float64), "KQ": arr(v.KQ, np.uint64),
+        "r": v.r, "v": v.v, "invr": v.invr,
     }
 
 

@@ -51,10 +51,35 @@ def test_tables_match_oracle(zig, O, dist, i_max):
         assert a[k] == b[k], k
 
 
+@pytest.mark.parametrize("dist", [0, 1])
+@pytest.mark.parametrize("i_max", [8, 16, 32, 64, 128, 256])
+def test_trad_tables_match_oracle(zig, O, dist, i_max):
+    """Traditional stack (the comparison sampler of Table 1): the library's
+    bisection on the top layer's area and the oracle's bisection on the
+    closure f_{n-1} = 1 give the same doubles; the quick-accept thresholds
+    are the integers below which k 2^-53 < k_i."""
+    a = zig.zig_get_trad_tables(dist, i_max)
+    b = O.trad_arrays(dist, i_max)
+    assert a["n"] == b["n"] == i_max and a["b"] == b["b"]
+    for k in ["X", "f", "W", "WS", "k"]:
+        assert np.array_equal(a[k].view(np.uint64), b[k].view(np.uint64)), k
+    for k in ["r", "v", "invr"]:
+        assert a[k] == b[k], k
+    kq = a["KQ"].astype(object)
+    for i in range(i_max):
+        ki = b["k"][i]
+        q = int(kq[i])
+        # the smallest integer q with q 2^-53 >= k_i
+        assert q * 2.0 ** -53 >= ki and (q == 0 or (q - 1) * 2.0 ** -53 < ki), i
+
+
 def test_bad_table_arguments(zig):
     for dist, i_max in [(2, 256), (0, 12), (0, 4), (1, 512), (0, 0)]:
         with pytest.raises(zig.ZigError) as e:
             zig.zig_get_tables(dist, i_max)
+        assert e.value.status == zig.ZIG_EINVAL
+        with pytest.raises(zig.ZigError) as e:
+            zig.zig_get_trad_tables(dist, i_max)
         assert e.value.status == zig.ZIG_EINVAL
     with pytest.raises(zig.ZigError):
         zig.zig_build_tables(100)
@@ -83,6 +108,13 @@ def test_fill_argument_validation(zig):
         lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"i_max": 100}),
         lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 96}),
         lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 512, "spl": 8}),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"flags": 4}),
+        # the traditional sampler: FP64 only, no trace, not with the accelerated variant, no moments
+        lambda: zig.zig_fill(0, 1, 1, 0, 10, 1.0, 1.0, fake, launch={"flags": zig.LAUNCH_TRADITIONAL}),
+        lambda: zig.zig_fill(1, 0, 1, 0, 10, 0.0, 1.0, fake, launch={"flags": 3}),
+        lambda: zig.zig_fill_trace(0, 0, 1, 0, 10, 1.0, 1.0, fake, fake, fake, fake, fake,
+                                   launch={"flags": zig.LAUNCH_TRADITIONAL}),
+        lambda: zig.zig_moments(0, 0, 1, 0, 10, 1.0, 1.0, fake, None, zig.Launch(0, 0, 0, zig.LAUNCH_TRADITIONAL)),
     ]
     for k, f in enumerate(bad):
         with pytest.raises(zig.ZigError) as e:
