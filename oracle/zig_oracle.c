@@ -76,6 +76,10 @@
  *      to float at the end.
  *  R14 Location-scale is one fused multiply-add after sampling:
  *      out = fma(scale, x, shift); exponential scale = RN(1/lambda).
+ *  R15 Traditional sampler (Table 1, right column; comparison only): the
+ *      first (i, U1) is the fast word of R10/R12; the wedge's U2 and each
+ *      restart's fresh word are the output's slow words in order; tails as
+ *      R8/R9 with traditional exponentials.
  */
 #include "zig_oracle.h"
 
