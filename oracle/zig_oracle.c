@@ -70,10 +70,13 @@
  *      block (n>>2, 0, 1) word n&3; slow word t of output n: block
  *      (n, t>>1, 2) words 0|1 (t even) or 2|3 (t odd).
  *  R13 Single precision (Appendix D item 4 names it without a definition):
- *      i = bits 0..b-1 of the 32-bit word; exp magnitude = bits 8..31,
- *      x = k * RN32(X_i) 2^-24; normal sign = bit 8, magnitude bits 9..31,
- *      x = k * RN32(X_i) 2^-23.  The slow path is the double one, rounded
- *      to float at the end.
+ *      i = bits 0..b-1 of the 32-bit word and s = max(b, 8); exp magnitude
+ *      = bits s..31, x = k * RN32(X_i) 2^-(32-s); normal sign = bit s,
+ *      magnitude bits s+1..31, x = k * RN32(X_i) 2^-(31-s) (for the
+ *      default 256 layers: bits 8..31 and 2^-24, sign bit 8, bits 9..31 and
+ *      2^-23; Appendix D item 1's 1024 layers take bits 10..31 and 2^-22,
+ *      sign bit 10, bits 11..31 and 2^-21).  The slow path is the double
+ *      one, rounded to float at the end.
  *  R14 Location-scale is one fused multiply-add after sampling:
  *      out = fma(scale, x, shift); exponential scale = RN(1/lambda).
  *  R15 Traditional sampler (Table 1, right column; comparison only): the
@@ -209,11 +212,12 @@ int orc_build_tables(int dist, uint32_t i_max, orc_tables* t) {
   if (dist != ORC_EXP && dist != ORC_NORMAL) return -1;
   uint32_t b = 0;
   while ((1u << b) < i_max) ++b;
-  if ((1u << b) != i_max || b < 3 || b > 8) return -1;
+  if ((1u << b) != i_max || b < 3 || b > 10) return -1;
   memset(t, 0, sizeof(*t));
   t->dist = dist;
   t->i_max = i_max;
   t->b = b;
+  const int s32 = b > 8 ? (int)b : 8; /* R13 */
 
   static __thread hp Xh[ORC_MAX_IMAX + 1], fh[ORC_MAX_IMAX + 1], Ah[ORC_MAX_IMAX + 1];
   const hp total = dens_total(dist);
@@ -269,7 +273,7 @@ int orc_build_tables(int dist, uint32_t i_max, orc_tables* t) {
   for (uint32_t i = 0; i < i_max; ++i) {
     if (i < L) {
       t->XS[i] = ldexp(t->X[i], -53);
-      t->XS32[i] = ldexpf((float)Xh[i], dist == ORC_EXP ? -24 : -23);
+      t->XS32[i] = ldexpf((float)Xh[i], dist == ORC_EXP ? s32 - 32 : s32 - 31);
     } else {
       t->XS[i] = 0.0;
       t->XS32[i] = 0.0f;
@@ -597,6 +601,7 @@ static float sample32(int dist, const orc_tables* ex, const orc_tables* nt, uint
   const orc_tables* t = (dist == ORC_EXP) ? ex : nt;
   uint32_t w = fast_word32(seed, n);
   uint32_t i = w & (t->i_max - 1);
+  const uint32_t s32 = t->b > 8 ? t->b : 8; /* R13 */
   float x;
   tr->layer = i;
   tr->region = -1;
@@ -604,15 +609,15 @@ static float sample32(int dist, const orc_tables* ex, const orc_tables* nt, uint
   tr->tests = 0;
   if (dist == ORC_EXP) {
     if (i < t->L)
-      x = (float)(w >> 8) * t->XS32[i];
+      x = (float)(w >> s32) * t->XS32[i];
     else
       x = (float)slow_magnitude(dist, ex, nt, seed, n, tr);
   } else {
     if (i < t->L)
-      x = (float)(w >> 9) * t->XS32[i];
+      x = (float)(w >> (s32 + 1)) * t->XS32[i];
     else
       x = (float)slow_magnitude(dist, ex, nt, seed, n, tr);
-    if ((w >> 8) & 1) x = -x;
+    if ((w >> s32) & 1) x = -x;
   }
   return fmaf((float)scale, x, (float)shift);
 }

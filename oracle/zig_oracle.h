@@ -41,7 +41,7 @@ typedef struct {
   double X[ORC_MAX_IMAX + 1];
   double f[ORC_MAX_IMAX + 1];
   double XS[ORC_MAX_IMAX];     /* X_i * 2^-53, zero for i >= L */
-  float XS32[ORC_MAX_IMAX];    /* RN32(X_i) * 2^-24 (exp) or 2^-23 (normal) */
+  float XS32[ORC_MAX_IMAX];    /* RN32(X_i) * 2^-(32-s) (exp) or 2^-(31-s) (normal), s = max(b, 8) */
   double W[ORC_MAX_IMAX + 1];  /* box widths  W_j = X_{j-1} - X_j, j = 1..L */
   double H[ORC_MAX_IMAX + 1];  /* box heights H_j = f_j - f_{j-1}, j = 1..L */
   uint64_t q[ORC_MAX_IMAX + 1];/* integer region weights, sum = 2^64 */

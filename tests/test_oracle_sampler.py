@@ -255,6 +255,45 @@ def test_small_tables_whole_distribution(O, dist, i_max):
     _moments_ok(dist, x)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("dist", [0, 1])
+def test_1024_layers_whole_distribution(O, dist, dtype):
+    """Appendix D item 1's 1024 layers, in both output types: exact CDF
+    and moments."""
+    x = O.fill(dist, dtype, 13, 5, 4 * 10 ** 6, 1.0, 0.0, threads=8, i_max=1024).astype(np.float64)
+    assert stats.kstest(x, "expon" if dist == 0 else "norm").pvalue > P_MIN
+    assert _chi2_equiprobable(_cdf(dist, x), 1000) > P_MIN
+    _moments_ok(dist, x)
+
+
+@pytest.mark.parametrize("dist", [0, 1])
+def test_fp32_bits_at_1024_layers(O, dist):
+    """With 10 index bits the single-precision magnitude starts at bit 10
+    (exponential, 22 bits) or 11 (normal, sign at bit 10, 21 bits): on the
+    fast path k = |x| / XS32_i is an integer below 2^(32-10) or 2^(31-10),
+    uniform, and its low bits are independent of the index bits 8..9 (a
+    magnitude that reused index bits would tie them together)."""
+    n = 10 ** 6
+    t = O.table_arrays(dist, 1024)
+    out, layer, region, words, tests = O.fill_trace(dist, 1, 17, 0, n, 1.0, 0.0, i_max=1024)
+    fast = region < 0
+    xs32 = t["XS32"].astype(np.float64)
+    kf = np.abs(out[fast].astype(np.float64)) / xs32[layer[fast]]
+    k = np.rint(kf).astype(np.int64)
+    assert np.all(np.abs(kf - k) < 0.25)
+    bits = 22 if dist == 0 else 21
+    assert k.min() >= 0 and k.max() < 2 ** bits and k.max() >= 2 ** bits - 2 ** (bits - 6)
+    assert stats.chisquare(np.bincount(k >> (bits - 8), minlength=256)).pvalue > P_MIN
+    table = np.zeros((4, 4))
+    np.add.at(table, ((layer[fast] >> 8) & 3, k & 3), 1)
+    assert stats.chi2_contingency(table)[1] > P_MIN
+    if dist == 1:
+        assert abs((out < 0).mean() - 0.5) < 4.5 * 0.5 / math.sqrt(n)
+        sign = np.zeros((4, 2))
+        np.add.at(sign, ((layer[fast] >> 8) & 3, (out[fast] < 0).astype(np.int64)), 1)
+        assert stats.chi2_contingency(sign)[1] > P_MIN
+
+
 @pytest.mark.parametrize("dist", [0, 1])
 def test_fp32_distribution(O, dist):
     x = O.fill(dist, 1, 21, 3, 4 * 10 ** 6, 1.0, 0.0, threads=8)

@@ -12,7 +12,7 @@ import pytest
 import mp_tables
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_pins.txt")
-IMAXES = [8, 16, 32, 64, 128, 256]
+IMAXES = [8, 16, 32, 64, 128, 256, 512, 1024]
 
 
 def pins():
@@ -33,6 +33,15 @@ def test_paper_layer_count(O):
     """L_max = 252 for the exponential at i_max = 256 (section 2)."""
     want = int(pins()["L_exp_256"].split()[0])
     assert O.table_arrays(0, 256)["L"] == want == 252
+
+
+def test_1024_layer_counts(O):
+    """Appendix D item 1's 1024 layers: four regions' worth of mass stays
+    outside the layers for the exponential (L = 1020, 0.39 % slow draws)
+    and three for the normal (L = 1021, 0.29 %); the independent mpmath
+    construction confirms the counts."""
+    assert O.table_arrays(0, 1024)["L"] == 1020
+    assert O.table_arrays(1, 1024)["L"] == 1021
 
 
 def test_paper_fast_exit_and_overhang_share(O):
@@ -119,7 +128,8 @@ def test_monotone_and_coverage(O, dist, i_max):
             assert abs(qv - A[j]) / A[j] < mp.mpf(10) ** -25, j
 
 
-@pytest.mark.parametrize("dist,i_max", [(0, 8), (1, 8), (0, 16), (1, 16), (0, 64), (1, 64), (0, 256), (1, 256)])
+@pytest.mark.parametrize("dist,i_max", [(0, 8), (1, 8), (0, 16), (1, 16), (0, 64), (1, 64), (0, 256), (1, 256),
+                                        (0, 1024), (1, 1024)])
 def test_independent_recomputation(O, dist, i_max):
     """A second construction (mpmath, solving for f by golden-section and
     bisection) rounds to the same doubles, bit for bit."""
@@ -132,10 +142,12 @@ def test_independent_recomputation(O, dist, i_max):
 
 
 @pytest.mark.parametrize("dist", [0, 1])
-@pytest.mark.parametrize("i_max", [8, 16, 256])
+@pytest.mark.parametrize("i_max", [8, 16, 256, 512, 1024])
 def test_derived_tables(O, dist, i_max):
     """Box widths and heights, the fast-path scale and its single-precision
-    copy, the tail constants."""
+    copy (the 32-bit word keeps s = max(b, 8) low bits for the index, so its
+    magnitude has 32 - s bits for the exponential and 31 - s for the
+    normal), the tail constants."""
     t = O.table_arrays(dist, i_max)
     L = t["L"]
     X, f = t["X"], t["f"]
@@ -146,7 +158,8 @@ def test_derived_tables(O, dist, i_max):
         assert t["W"][j] > 0 and t["H"][j] > 0
     for i in range(L):
         assert t["XS"][i] == math.ldexp(X[i], -53)
-        e = -24 if dist == 0 else -23
+        s32 = max(t["b"], 8)
+        e = s32 - 32 if dist == 0 else s32 - 31
         assert t["XS32"][i] == np.float32(math.ldexp(float(np.float32(mp.mpf(t["hpX"][i]))), e))
     assert np.all(t["XS"][L:] == 0)
     assert t["X0"] == X[0]
