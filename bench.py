@@ -316,6 +316,34 @@ def traditional_ab(torch, zig):
     return res
 
 
+def layers_ab(torch, zig):
+    """Appendix D item 1 on this GPU: the headline fills (2^30, FP64 and
+    FP32) with 1024 layers against 256, each at the default shape, the
+    1024-layer kernels also at their best of a few shapes."""
+    res = {}
+    shapes = [(0, 0), (256, 8), (512, 4), (512, 2), (1024, 2)]
+    for dtype, tname, esize in [(0, "f64", 8), (1, "f32", 4)]:
+        out = torch.empty(N_C3, dtype=torch.float64 if dtype == 0 else torch.float32, device="cuda")
+        for dist, name, seed, p0, p1 in [(0, "exp", 11, 2.5, 0.0), (1, "normal", 12, -1.0, 3.0)]:
+            _, dd = timed_fills(torch, zig, [(lambda: zig.fill(out, dist, seed, 0, p0, p1), N_C3 * esize)], 10, 3)
+            ms256 = float(np.mean(dd))
+            wide = {}
+            for wg, spl in shapes:
+                lw = zig.Launch(1024, wg, spl, 0)
+                _, dd = timed_fills(torch, zig, [(lambda: zig.fill(out, dist, seed, 0, p0, p1, launch=lw),
+                                                  N_C3 * esize)], 10, 3)
+                wide["default" if wg == 0 else "%dx%d" % (wg, spl)] = round(float(np.mean(dd)), 4)
+            best = min(wide, key=wide.get)
+            res["%s_%s" % (name, tname)] = {
+                "ms_256_layers": round(ms256, 4), "ms_1024_layers": wide, "best_1024": best,
+                "ratio_1024_over_256": round(wide[best] / ms256, 4),
+                "slow_share": {"256": 1 - zig.zig_get_tables(dist, 256)["L"] / 256.0,
+                               "1024": 1 - zig.zig_get_tables(dist, 1024)["L"] / 1024.0}}
+        del out
+        torch.cuda.empty_cache()
+    return res
+
+
 def autotune_report(zig):
     """Runs the autotuner on this device (cache in a temporary file) and
     reports, per (dist, dtype, size class), the chosen shape and its time
@@ -473,6 +501,9 @@ def main():
         log("modified vs traditional ziggurat")
         result["traditional_ab"] = traditional_ab(torch, zig)
         log("traditional_ab: %s" % json.dumps(result["traditional_ab"]))
+        log("1024 against 256 layers")
+        result["layers_1024"] = layers_ab(torch, zig)
+        log("layers_1024: %s" % json.dumps(result["layers_1024"]))
         log("autotuner")
         result["autotune"] = autotune_report(zig)
         log("autotune: %s" % json.dumps(result["autotune"]))

@@ -58,7 +58,8 @@ extern "C" {
  * i_max layers (section 2: equal-area layers solved from
  * X_i (P(X_i) - P(X_{i-1})) = 1/i_max, computed in 113-bit precision and
  * rounded to double as in Appendix B), and uploads them to the current
- * device.  i_max must be a power of two in [8, 256].  Idempotent and
+ * device.  i_max must be a power of two in [8, 1024] (Appendix D item 1
+ * names 1024; 256 is the paper's choice).  Idempotent and
  * thread-safe; the tables are immutable afterwards.  Fills call it
  * implicitly with the i_max they use (256 by default).
  * Errors: ZIG_EINVAL (bad i_max), ZIG_ENOTABLES, ZIG_EHIP, ZIG_ENOMEM. */
@@ -70,7 +71,8 @@ int zig_build_tables(uint32_t i_max);
  * regions are j = 0 (tail), 1..L-1 (overhang right of layer j), L (cap).
  *   X, f      L+1 entries: layer lengths and heights f_i = P(X_i)
  *   XS        i_max entries: X_i * 2^-53 (0 for i >= L)
- *   XS32      i_max entries: RN32(X_i) * 2^-24 (exp) or 2^-23 (normal)
+ *   XS32      i_max entries: RN32(X_i) * 2^-(32-s) (exp) or 2^-(31-s)
+ *             (normal), s = max(b, 8): 2^-24 / 2^-23 up to 256 layers
  *   W, H      L+1 entries, index 0 unused: box width X_{j-1} - X_j and
  *             height f_j - f_{j-1} of region j
  *   q         L+1 entries: integer region weights, sum 2^64
@@ -154,6 +156,12 @@ int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dt
  * lanes per workgroup and spl in {1,2,4,8} Philox blocks per lane make a
  * tile of wg * spl blocks (at most 2048), which is also the depth of the
  * per-workgroup slow-output queue.
+ * i_max above 256 (512 or 1024 layers) takes b = log2 i_max index bits:
+ * the FP64 word keeps its layout (sign bit 10, magnitude bits 11..63);
+ * the FP32 word gives bits 0..b-1 to the index, the exponential's
+ * magnitude bits b..31 (x = k RN32(X_i) 2^-(32-b)), the normal's sign bit b
+ * and magnitude bits b+1..31 (2^-(31-b)).  Such tables run the plain
+ * modified sampler only (no flags).
  * flags: ZIG_LAUNCH_NORMAL_ACCEL selects, for the normal distribution, an
  * accelerated overhang sampler that goes beyond the paper's text (which
  * gives the chord split for the exponential only, section 2): in the
@@ -217,8 +225,9 @@ int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
  * blocks l, l + 256, ..., l + 1792 in order; the 256 lane sums are reduced
  * by halving (v[l] += v[l + s] for s = 128, 64, ..., 1); groups of 256
  * tiles likewise (the last one padded with +0); the total is +0 plus the
- * group sums in order.  launch may be NULL; only launch->i_max is honoured
- * (wg and spl must be 0 or 256 and 8).  Asynchronous on `stream`; uses
+ * group sums in order.  launch may be NULL; only launch->i_max (up to 256)
+ * and ZIG_LAUNCH_NORMAL_ACCEL are honoured (wg and spl must be 0 or 256
+ * and 8).  Asynchronous on `stream`; uses
  * 2.6 MB of device scratch per stream, kept until the process ends.
  * Errors: as zig_fill (sums in place of out). */
 int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,

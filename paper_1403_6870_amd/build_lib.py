@@ -18,7 +18,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HOST_SRCS = ["zig_tables.cpp", "zig_tune.cpp", "zig_api.cpp", "zig_batch.cpp", "zig_server.cpp"]
-HIP_SRCS = ["zig_fill.hip", "zig_batch.hip", "zig_moments.hip", "zig_trad.hip"]
+HIP_SRCS = ["zig_fill.hip", "zig_batch.hip", "zig_moments.hip", "zig_trad.hip", "zig_fill_wide.hip"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]

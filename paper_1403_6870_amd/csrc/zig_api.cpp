@@ -77,7 +77,7 @@ void to_device_layout(const HostTable& h, DevTable* d) {
 
 // device copy for the current device; returns the pair [exp, normal]
 int device_tables(uint32_t i_max, const DevTable** out) {
-  if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 1024]");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
@@ -257,7 +257,7 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   zig_launch cfg = {0, 0, 0, 0};
   if (launch) cfg = *launch;
   const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
-  if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 1024]");
   if (cfg.flags & ~(ZIG_LAUNCH_NORMAL_ACCEL | ZIG_LAUNCH_TRADITIONAL))
     return fail(ZIG_EINVAL, "unknown launch flags");
   const bool trad = (cfg.flags & ZIG_LAUNCH_TRADITIONAL) != 0;
@@ -265,8 +265,12 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
     if (cfg.flags & ZIG_LAUNCH_NORMAL_ACCEL)
       return fail(ZIG_EINVAL, "ZIG_LAUNCH_TRADITIONAL does not combine with ZIG_LAUNCH_NORMAL_ACCEL");
     if (dtype != kF64) return fail(ZIG_EINVAL, "the traditional sampler is FP64 only");
+    if (i_max > kLdsLayers) return fail(ZIG_EINVAL, "the traditional sampler takes i_max up to 256");
     if (trace) return fail(ZIG_EINVAL, "the traditional sampler has no trace");
   }
+  const bool wide = i_max > kLdsLayers;
+  if (wide && (cfg.flags & ZIG_LAUNCH_NORMAL_ACCEL))
+    return fail(ZIG_EINVAL, "the accelerated normal variant takes i_max up to 256");
   if (n == 0) return ZIG_OK;
   if (out == nullptr) return fail(ZIG_EINVAL, "out is null");
   const uint64_t esize = dtype == kF64 ? 8 : 4;
@@ -339,8 +343,9 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
     a.blk0 = blk0 + start * tile;
     a.tiles = (uint32_t)((tiles - start < chunk) ? tiles - start : chunk);
     a.chunk = sh.chunk;
-    int e = trad ? launch_trad(dist, sh.wg, sh.spl, a, stream)
-                 : launch_fill(dist, dtype, sh.wg, sh.spl, trace, a, stream);
+    int e = trad   ? launch_trad(dist, sh.wg, sh.spl, a, stream)
+            : wide ? launch_fill_wide(dist, dtype, sh.wg, sh.spl, trace, a, stream)
+                   : launch_fill(dist, dtype, sh.wg, sh.spl, trace, a, stream);
     if (e != 0)
       return fail(ZIG_EHIP, std::string("fill launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
   }
@@ -375,7 +380,7 @@ int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out) {
   zig::g_error.clear();
   if (out == nullptr) return zig::fail(ZIG_EINVAL, "out is null");
   if (dist > 1) return zig::fail(ZIG_EINVAL, "unknown distribution");
-  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 1024]");
   std::lock_guard<std::mutex> lk(zig::g_mu);
   zig::HostPair* hp = nullptr;
   int r = zig::host_tables_locked(i_max, &hp);
@@ -409,7 +414,8 @@ int zig_get_trad_tables(uint32_t dist, uint32_t i_max, zig_trad_view* out) {
   zig::g_error.clear();
   if (out == nullptr) return zig::fail(ZIG_EINVAL, "out is null");
   if (dist > 1) return zig::fail(ZIG_EINVAL, "unknown distribution");
-  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (!zig::valid_imax(i_max) || i_max > zig::kLdsLayers)
+    return zig::fail(ZIG_EINVAL, "the traditional sampler takes i_max a power of two in [8, 256]");
   std::lock_guard<std::mutex> lk(zig::g_mu);
   zig::TradPair* tp = nullptr;
   int r = zig::host_trad_locked(i_max, &tp);
@@ -467,9 +473,10 @@ int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_ind
   zig_launch cfg = {0, 0, 0, 0};
   if (launch) cfg = *launch;
   const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
-  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 256]");
+  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 1024]");
   if (cfg.flags & ZIG_LAUNCH_TRADITIONAL)
     return zig::fail(ZIG_EINVAL, "the moments kernel runs the modified sampler only");
+  if (i_max > zig::kLdsLayers) return zig::fail(ZIG_EINVAL, "the moments kernel takes i_max up to 256");
   if (cfg.flags & ~ZIG_LAUNCH_NORMAL_ACCEL) return zig::fail(ZIG_EINVAL, "unknown launch flags");
   if ((cfg.wg && cfg.wg != 256) || (cfg.spl && cfg.spl != 8))
     return zig::fail(ZIG_EINVAL, "the moments kernel runs 256 lanes x 8 blocks (its summation order)");

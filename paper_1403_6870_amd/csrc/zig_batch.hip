@@ -25,12 +25,12 @@ namespace {
 
 template <int WG, int S>
 struct BatchLds {
-  double xs64[2][kMaxLayers];
-  float xs32[2][kMaxLayers];
-  double X[2][kMaxLayers + 1];
-  double f[2][kMaxLayers + 1];
-  uint64_t T[2][kMaxLayers];
-  uint32_t A[2][kMaxLayers];
+  double xs64[2][kLdsLayers];
+  float xs32[2][kLdsLayers];
+  double X[2][kLdsLayers + 1];
+  double f[2][kLdsLayers + 1];
+  uint64_t T[2][kLdsLayers];
+  uint32_t A[2][kLdsLayers];
   double2 stage[WG * S];
   uint64_t slowmap[S * 4 * (WG / 64)];  // enough for 4 outputs per block
   uint32_t prefix[S * 4 * (WG / 64) + 1];
@@ -61,13 +61,13 @@ __global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
   const uint32_t tid = threadIdx.x;
   for (uint32_t d = 0; d < 2; ++d) {
     const DevTable* tb = ba.tabs + d;
-    for (uint32_t i = tid; i < kMaxLayers; i += WG) {
+    for (uint32_t i = tid; i < kLdsLayers; i += WG) {
       sh.xs64[d][i] = tb->XS[i];
       sh.xs32[d][i] = tb->XS32[i];
       sh.T[d][i] = tb->T[i];
       sh.A[d][i] = tb->A[i];
     }
-    for (uint32_t i = tid; i <= kMaxLayers; i += WG) {
+    for (uint32_t i = tid; i <= kLdsLayers; i += WG) {
       sh.X[d][i] = tb->X[i];
       sh.f[d][i] = tb->f[i];
     }

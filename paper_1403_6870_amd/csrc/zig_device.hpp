@@ -245,10 +245,11 @@ __device__ __forceinline__ double slow_magnitude(const TabView& own, const TabVi
   return m;
 }
 
-// Sign of normal output g (FP64: bit 10 of its fast word; FP32: bit 8),
-// recomputed from its fast block for the rare outputs on the slow path.
+// Sign of normal output g (FP64: bit 10 of its fast word; FP32: bit s32,
+// 8 unless the table has more than 256 layers), recomputed from its fast
+// block for the rare outputs on the slow path.
 template <uint32_t DT>
-__device__ __forceinline__ bool normal_sign(uint64_t g, uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ bool normal_sign(uint64_t g, uint32_t k0, uint32_t k1, uint32_t s32) {
   if constexpr (DT == kF64) {
     const uint64_t m = g >> 1;
     uint32_t c0 = (uint32_t)m, c1 = (uint32_t)(m >> 32), c2 = 0u, c3 = 0u;
@@ -261,7 +262,7 @@ __device__ __forceinline__ bool normal_sign(uint64_t g, uint32_t k0, uint32_t k1
     philox10(c0, c1, c2, c3, k0, k1);
     const uint32_t r = g & 3;
     const uint32_t w = r == 0 ? c0 : r == 1 ? c1 : r == 2 ? c2 : c3;
-    return (w >> 8) & 1u;
+    return (w >> s32) & 1u;
   }
 }
 

@@ -56,15 +56,19 @@ struct FillShape {
   static_assert(WG % 64 == 0 && NWORD <= 1024 && TILE * 16 <= 32768, "tile shape");
 };
 
-// LDS of one workgroup
-template <uint32_t DT, int WG, int S>
+// LDS of one workgroup.  CAP is the largest table it serves: up to
+// kLdsLayers the slow-path tables (X, f, alias) are staged here too; wider
+// tables keep only the fast-path table here and the slow paths, which
+// serve a few outputs in a thousand, read the rest from device memory.
+template <uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers>
 struct FillLds {
   using Sh = FillShape<DT, WG, S>;
-  typename Sh::OutT xs[kMaxLayers];
-  double X[kMaxLayers + 1];
-  double f[kMaxLayers + 1];
-  uint64_t T[kMaxLayers];
-  uint32_t A[kMaxLayers];
+  static constexpr uint32_t SLOW = CAP <= kLdsLayers ? CAP : 1;
+  typename Sh::OutT xs[CAP];
+  double X[SLOW + 1];
+  double f[SLOW + 1];
+  uint64_t T[SLOW];
+  uint32_t A[SLOW];
   typename Sh::VecT stage[Sh::TILE];
   uint64_t slowmap[Sh::NWORD];
   uint32_t prefix[Sh::NWORD + 1];
@@ -90,28 +94,32 @@ struct TileLds {
   uint32_t* prefix;
 };
 
-template <uint32_t DIST, uint32_t DT, int WG, int S>
-__device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG, S>& sh) {
+template <uint32_t DIST, uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers>
+__device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG, S, CAP>& sh) {
   const DevTable* tb = a.tab;
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < kMaxLayers; i += WG) {
+  for (uint32_t i = tid; i < CAP; i += WG) {
     if constexpr (DT == kF64)
       sh.xs[i] = tb->XS[i];
     else
       sh.xs[i] = tb->XS32[i];
-    sh.T[i] = tb->T[i];
-    sh.A[i] = tb->A[i];
-  }
-  for (uint32_t i = tid; i <= kMaxLayers; i += WG) {
-    sh.X[i] = tb->X[i];
-    sh.f[i] = tb->f[i];
   }
   FillCtx c;
   c.own = dev::global_view(tb);
-  c.own.X = sh.X;
-  c.own.f = sh.f;
-  c.own.T = sh.T;
-  c.own.A = sh.A;
+  if constexpr (CAP <= kLdsLayers) {
+    for (uint32_t i = tid; i < CAP; i += WG) {
+      sh.T[i] = tb->T[i];
+      sh.A[i] = tb->A[i];
+    }
+    for (uint32_t i = tid; i <= CAP; i += WG) {
+      sh.X[i] = tb->X[i];
+      sh.f[i] = tb->f[i];
+    }
+    c.own.X = sh.X;
+    c.own.f = sh.f;
+    c.own.T = sh.T;
+    c.own.A = sh.A;
+  }
   if constexpr (DT == kF64) c.own.XS = sh.xs;
   c.fast = sh.xs;
   c.ex = dev::global_view(a.etab);
@@ -128,7 +136,7 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
 template <uint32_t DIST, int WG, int S>
 __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a, FillLds<kF64, WG, S>& sh) {
   const DevTrad* tb = a.ttab;
-  for (uint32_t i = threadIdx.x; i < kMaxLayers; i += WG) {
+  for (uint32_t i = threadIdx.x; i < kLdsLayers; i += WG) {
     sh.xs[i] = tb->WS[i];
     sh.T[i] = tb->KQ[i];
     sh.f[i] = tb->f[i];
@@ -158,8 +166,12 @@ __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a, FillLds<k
 // With TRAD set (FP64 only) the sampler is the traditional ziggurat: the
 // fast word quick-accepts when its magnitude bits lie below the layer's
 // threshold, and phase B runs the traditional slow path from that word.
+//
+// WIDE marks tables of more than 256 layers: a 32-bit word then gives
+// s = b > 8 low bits to the index, so its magnitude starts at bit s (the
+// normal's sign sits at bit s); otherwise s = 8.
 template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool MOM = false, bool ACCEL = false,
-          bool TRAD = false>
+          bool TRAD = false, bool WIDE = false>
 __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t,
                                           double* msum = nullptr) {
   using Sh = FillShape<DT, WG, S>;
@@ -176,6 +188,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   const uint32_t wave = tid >> 6;
   const uint32_t L = TRAD ? 0u : c.own.L;
   const uint32_t imask = TRAD ? c.tr.imask : c.own.imask;
+  const uint32_t s32 = WIDE ? (c.own.b > 8u ? c.own.b : 8u) : 8u;
   const float fscale = (float)c.scale, fshift = (float)c.shift;
   OutT* const out = static_cast<OutT*>(a.out);
   VecT* const stage = static_cast<VecT*>(sh.stage);
@@ -219,10 +232,10 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
           i = w & imask;
           miss = i >= L;
           if constexpr (DIST == kDistExp) {
-            x = (float)(w >> 8) * xs[i];
+            x = (float)(w >> s32) * xs[i];
           } else {
-            x = (float)(w >> 9) * xs[i];
-            if ((w >> 8) & 1u) x = -x;
+            x = (float)(w >> (s32 + 1u)) * xs[i];
+            if ((w >> s32) & 1u) x = -x;
           }
         }
         // a slow output's value here is a placeholder that phase B replaces;
@@ -327,7 +340,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
     if constexpr (TRAD) {
       mag = dev::trad_slow<DIST>(c.tr, c.trex, g, c.k0, c.k1, neg, words, tests);
     } else {
-      if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, c.k0, c.k1);
+      if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, c.k0, c.k1, s32);
       mag = dev::slow_magnitude<DIST, ACCEL>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
     }
     OutT x = (OutT)mag;
@@ -434,14 +447,16 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
 // device on that address), so the tiles in flight stay a window that
 // sweeps through the output in address order.  The last workgroup to leave
 // resets the counters for the next launch on the same stream.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false>
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
+          bool WIDE = false>
 __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
-  __shared__ FillLds<DT, WG, S> sh;
+  static_assert(!(WIDE && (TRAD || ACCEL)), "wide tables: the plain modified sampler");
+  __shared__ FillLds<DT, WG, S, WIDE ? kMaxLayers : kLdsLayers> sh;
   const FillCtx c = [&] {
     if constexpr (TRAD)
       return load_trad_tables<DIST, WG, S>(a, sh);
     else
-      return load_tables<DIST, DT, WG, S>(a, sh);
+      return load_tables<DIST, DT, WG, S, WIDE ? kMaxLayers : kLdsLayers>(a, sh);
   }();
   TileLds tl;
   tl.stage = sh.stage;
@@ -454,7 +469,7 @@ __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
     if (t0 >= a.tiles) break;
     const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
     for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, WG, S, TRACE, false, ACCEL, TRAD>(a, c, tl, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE, false, ACCEL, TRAD, WIDE>(a, c, tl, (uint32_t)t);
       __syncthreads();
     }
   }
@@ -494,9 +509,10 @@ int resident_groups(K kernel, int wg, size_t lds, int* out) {
 
 // Launch of one fill-kernel variant: as many persistent workgroups as are
 // resident on the device, fewer when the launch has fewer counter steps.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false>
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
+          bool WIDE = false>
 int launch_one(const FillArgs& args, hipStream_t st) {
-  auto kernel = fill_kernel<DIST, DT, WG, S, TRACE, ACCEL, TRAD>;
+  auto kernel = fill_kernel<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE>;
   int groups = 0;
   int e = resident_groups(kernel, WG, 0, &groups);
   if (e != 0) return e;
@@ -511,6 +527,26 @@ int launch_one(const FillArgs& args, hipStream_t st) {
   const uint32_t grid = steps < (uint64_t)groups ? (uint32_t)steps : (uint32_t)groups;
   hipLaunchKernelGGL(kernel, dim3(grid), dim3(WG), 0, st, a);
   return (int)hipGetLastError();
+}
+
+// Launch of the variant with workgroup size wg and spl blocks per lane:
+// every shape of up to 2048 blocks per tile for plain fills, three for the
+// trace build.
+template <uint32_t DIST, uint32_t DT, bool TRACE, bool ACCEL = false, bool TRAD = false, bool WIDE = false>
+int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
+#define ZIG_SHAPE(W, S_) \
+  if (wg == W && spl == S_) return launch_one<DIST, DT, W, S_, TRACE, ACCEL, TRAD, WIDE>(a, st);
+  if constexpr (!TRACE) {
+    ZIG_SHAPE(64, 1) ZIG_SHAPE(64, 2) ZIG_SHAPE(64, 4) ZIG_SHAPE(64, 8)
+    ZIG_SHAPE(128, 1) ZIG_SHAPE(128, 2) ZIG_SHAPE(128, 4) ZIG_SHAPE(128, 8)
+    ZIG_SHAPE(256, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4) ZIG_SHAPE(256, 8)
+    ZIG_SHAPE(512, 1) ZIG_SHAPE(512, 2) ZIG_SHAPE(512, 4)
+    ZIG_SHAPE(1024, 1) ZIG_SHAPE(1024, 2)
+  } else {
+    ZIG_SHAPE(64, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4)
+  }
+#undef ZIG_SHAPE
+  return (int)hipErrorInvalidConfiguration;
 }
 
 }  // namespace zig

@@ -7,7 +7,11 @@
 
 namespace zig {
 
-constexpr uint32_t kMaxLayers = 256;  // largest supported i_max
+constexpr uint32_t kMaxLayers = 1024;  // largest supported i_max
+// Largest i_max whose slow-path tables the standard kernels keep in LDS;
+// larger tables (Appendix D item 1's 1024 layers) run in the wide kernels,
+// which keep only the fast-path table there.
+constexpr uint32_t kLdsLayers = 256;
 constexpr uint32_t kDistExp = 0;
 constexpr uint32_t kDistNormal = 1;
 constexpr uint32_t kF64 = 0;
@@ -32,7 +36,7 @@ struct DevTable {
 };
 
 // g++ builds the host side and hipcc the device side: both must agree
-static_assert(sizeof(DevTable) == 14424, "DevTable layout");
+static_assert(sizeof(DevTable) == 57432, "DevTable layout");
 
 // Host copy with the same content plus the quantities only tests need.
 struct HostTable {
@@ -61,9 +65,9 @@ std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out);
 struct DevTrad {
   uint32_t dist, n, b, pad;
   double r, invr;
-  double WS[kMaxLayers];
-  uint64_t KQ[kMaxLayers];
-  double f[kMaxLayers];
+  double WS[kLdsLayers];
+  uint64_t KQ[kLdsLayers];
+  double f[kLdsLayers];
 };
 static_assert(sizeof(DevTrad) == 6176, "DevTrad layout");
 
@@ -74,7 +78,8 @@ struct HostTrad {
   double r = 0.0, v = 0.0, invr = 0.0;
 };
 
-// Builds the traditional stack of n layers in binary128 (zig_tables.cpp).
+// Builds the traditional stack of n <= kLdsLayers layers in binary128
+// (zig_tables.cpp).
 std::string build_host_trad(uint32_t dist, uint32_t n, HostTrad* out);
 
 // Kernel-side argument block of a plain fill.
@@ -111,6 +116,11 @@ struct FillArgs {
 // Returns 0 or a hipError_t value.
 int launch_fill(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, const FillArgs& a,
                 void* stream);
+
+// The same for tables of more than kLdsLayers layers (zig_fill_wide.hip);
+// no accelerated variant.
+int launch_fill_wide(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, bool trace, const FillArgs& a,
+                     void* stream);
 
 // The same for the traditional sampler, FP64 only (zig_trad.hip); a.ttab
 // and a.tetab set.

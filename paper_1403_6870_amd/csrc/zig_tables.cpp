@@ -101,7 +101,7 @@ std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out) {
   if (dist != kDistExp && dist != kDistNormal) return "unknown distribution";
   uint32_t b = 0;
   while (b < 31 && (1u << b) < i_max) ++b;
-  if ((1u << b) != i_max || i_max < 8 || i_max > kMaxLayers) return "i_max must be a power of two in [8, 256]";
+  if ((1u << b) != i_max || i_max < 8 || i_max > kMaxLayers) return "i_max must be a power of two in [8, 1024]";
 
   const Density P{dist};
   const q128 area = P.total() / i_max;
@@ -138,7 +138,10 @@ std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out) {
   }
   t.XS.assign(i_max, 0.0);
   t.XS32.assign(i_max, 0.0f);
-  const int e32 = dist == kDistExp ? -24 : -23;
+  // the 32-bit word keeps its low s = max(b, 8) bits for the index: the
+  // magnitude has 32 - s bits (exponential) or 31 - s after the sign bit s
+  const int s32 = b > 8 ? (int)b : 8;
+  const int e32 = dist == kDistExp ? s32 - 32 : s32 - 31;
   for (uint32_t i = 0; i < L; ++i) {
     t.XS[i] = std::ldexp(t.X[i], -53);
     t.XS32[i] = std::ldexp((float)Xq[i], e32);
@@ -269,7 +272,7 @@ std::string build_host_trad(uint32_t dist, uint32_t n, HostTrad* out) {
   if (dist != kDistExp && dist != kDistNormal) return "unknown distribution";
   uint32_t b = 0;
   while (b < 31 && (1u << b) < n) ++b;
-  if ((1u << b) != n || n < 8 || n > kMaxLayers) return "i_max must be a power of two in [8, 256]";
+  if ((1u << b) != n || n < 8 || n > kLdsLayers) return "the traditional sampler takes i_max a power of two in [8, 256]";
   const Density P{dist};
   auto inverse = [&](q128 y) { return dist == kDistExp ? -logq(y) : sqrtq(-2 * logq(y)); };
   std::vector<q128> X(n), f(n);

@@ -1,0 +1,79 @@
+"""GPU parity of the wide-table kernels (512 and 1024 layers, Appendix D
+item 1) against the oracle, through the C ABI: per-output traces (layer,
+first region, slow words, density tests), whole fills at several launch
+shapes with a ragged tail, and 2^30 fills in sampled chunks.
+
+Bar: as for the 256-layer fills, FP64 outputs bit-identical on the fast
+path and within 4 ulp on the slow paths with identical decisions; FP32
+within 2 ulp."""
+import numpy as np
+import pytest
+
+from helpers import EXP, F32, F64, NORMAL, gpu_fill, oracle_fill, parity, to_np
+
+pytestmark = pytest.mark.gpu
+
+ULP = {F64: 4, F32: 2}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_1403_6870_amd import zig
+    assert torch.cuda.is_available()
+    return torch, zig
+
+
+@pytest.mark.parametrize("i_max", [512, 1024])
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("dist", [EXP, NORMAL])
+def test_trace_parity(O, env, dist, dtype, i_max):
+    torch, zig = env
+    n = (1 << 18) + 77
+    first = 1 << 33
+    p0, p1 = (1.0, 0.0) if dist == EXP else (0.0, 1.0)
+    out = torch.empty(n, dtype=torch.float64 if dtype == F64 else torch.float32, device="cuda")
+    out, layer, region, words, tests = zig.fill_trace(out, dist, 5, first, p0, p1, launch={"i_max": i_max})
+    w_out, w_layer, w_region, w_words, w_tests = O.fill_trace(dist, dtype, 5, first, n, 1.0, 0.0, i_max=i_max)
+    assert np.array_equal(to_np(layer).view(np.uint32), w_layer)
+    assert np.array_equal(to_np(region), w_region)
+    assert np.array_equal(to_np(words).view(np.uint32), w_words)
+    assert np.array_equal(to_np(tests).view(np.uint32), w_tests)
+    nd, mu = parity(to_np(out), w_out, ULP[dtype])
+    print("wide trace d%d t%d i%d: %d not bit-identical, max %d ulp" % (dist, dtype, i_max, nd, mu), flush=True)
+
+
+@pytest.mark.parametrize("wg,spl", [(0, 0), (64, 1), (256, 8), (1024, 2)])
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("dist", [EXP, NORMAL])
+def test_fill_parity(O, env, dist, dtype, wg, spl):
+    """Several tiles plus a ragged tail at an odd first index, 1024 layers,
+    non-trivial parameters."""
+    n = (1 << 20) + 12345
+    p0, p1 = (2.5, 0.0) if dist == EXP else (-1.0, 3.0)
+    got = to_np(gpu_fill(dist, dtype, 21 + dist, 7, n, p0, p1, launch={"i_max": 1024, "wg": wg, "spl": spl}))
+    want = oracle_fill(O, dist, dtype, 21 + dist, 7, n, p0, p1, i_max=1024)
+    parity(got, want, ULP[dtype])
+
+
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("dist", [EXP, NORMAL])
+def test_full_size_sampled(O, env, dist, dtype):
+    """2^30 outputs with 1024 layers, default shape (the configuration the
+    comparison with 256 layers times): head, tail and 16 random chunks
+    against the oracle."""
+    torch, zig = env
+    n = 1 << 30
+    seed = 11 if dist == EXP else 12
+    p0, p1 = (2.5, 0.0) if dist == EXP else (-1.0, 3.0)
+    out = gpu_fill(dist, dtype, seed, 0, n, p0, p1, launch={"i_max": 1024})
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    size = 1 << 14
+    starts = [0, n - size] + sorted(int(v) for v in rng.integers(0, n - size, size=16))
+    for s in starts:
+        got = out[s:s + size].cpu().numpy()
+        parity(got, oracle_fill(O, dist, dtype, seed, s, size, p0, p1, i_max=1024), ULP[dtype])
+    del out
+    torch.cuda.empty_cache()

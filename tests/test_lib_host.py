@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(zig):
 
 
 @pytest.mark.parametrize("dist", [0, 1])
-@pytest.mark.parametrize("i_max", [8, 16, 32, 64, 128, 256])
+@pytest.mark.parametrize("i_max", [8, 16, 32, 64, 128, 256, 512, 1024])
 def test_tables_match_oracle(zig, O, dist, i_max):
     """The library's binary128 construction (bracketed Newton) and the
     oracle's (bisection) give the same doubles and integers."""
@@ -74,10 +74,11 @@ def test_trad_tables_match_oracle(zig, O, dist, i_max):
 
 
 def test_bad_table_arguments(zig):
-    for dist, i_max in [(2, 256), (0, 12), (0, 4), (1, 512), (0, 0)]:
+    for dist, i_max in [(2, 256), (0, 12), (0, 4), (1, 2048), (0, 0)]:
         with pytest.raises(zig.ZigError) as e:
             zig.zig_get_tables(dist, i_max)
         assert e.value.status == zig.ZIG_EINVAL
+    for dist, i_max in [(2, 256), (0, 12), (0, 4), (1, 512), (0, 1024), (0, 0)]:
         with pytest.raises(zig.ZigError) as e:
             zig.zig_get_trad_tables(dist, i_max)
         assert e.value.status == zig.ZIG_EINVAL
@@ -115,6 +116,11 @@ def test_fill_argument_validation(zig):
         lambda: zig.zig_fill_trace(0, 0, 1, 0, 10, 1.0, 1.0, fake, fake, fake, fake, fake,
                                    launch={"flags": zig.LAUNCH_TRADITIONAL}),
         lambda: zig.zig_moments(0, 0, 1, 0, 10, 1.0, 1.0, fake, None, zig.Launch(0, 0, 0, zig.LAUNCH_TRADITIONAL)),
+        # tables of more than 256 layers: plain fills only
+        lambda: zig.zig_fill(1, 0, 1, 0, 10, 0.0, 1.0, fake, launch={"i_max": 1024, "flags": 1}),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"i_max": 512, "flags": zig.LAUNCH_TRADITIONAL}),
+        lambda: zig.zig_moments(0, 0, 1, 0, 10, 1.0, 1.0, fake, None, zig.Launch(1024, 0, 0, 0)),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"i_max": 2048}),
     ]
     for k, f in enumerate(bad):
         with pytest.raises(zig.ZigError) as e:
