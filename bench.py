@@ -431,6 +431,11 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     log("headline: %.2f Gsamples/s; fill kernel exp %.3f ms, normal %.3f ms (%.0f GB/s)" %
         (value, d[:, 0].mean(), d[:, 1].mean(), achieved))
+    # the store ceiling: a plain store kernel (torch's fill_) over the same
+    # 8 GiB buffer, timed the same way
+    _, ds = timed_fills(torch, zig, [(lambda: out_n.fill_(1.0), N_C3 * 8)], 10, 3)
+    store_gbs = N_C3 * 8 / (float(np.mean(ds)) * 1e-3) / 1e9
+    log("store ceiling (fill_ of 8 GiB): %.0f GB/s" % store_gbs)
     del out_e, out_n
     torch.cuda.empty_cache()
     if args.copy_calibration:
@@ -457,7 +462,9 @@ def main():
                      "bytes_per_launch": bytes_per_launch,
                      "per_launch_ms": {"exp": round(float(d[:, 0].mean()), 4),
                                        "normal": round(float(d[:, 1].mean()), 4)},
-                     "exp_fill_GB/s": round(bytes_per_launch / (float(d[:, 0].mean()) * 1e-3) / 1e9, 1)},
+                     "exp_fill_GB/s": round(bytes_per_launch / (float(d[:, 0].mean()) * 1e-3) / 1e9, 1),
+                     "store_ceiling_GB/s": round(store_gbs, 1),
+                     "frac_of_store_ceiling": round(achieved / store_gbs, 4)},
     }
 
     if not args.no_extra:

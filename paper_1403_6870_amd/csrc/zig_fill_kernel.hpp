@@ -53,7 +53,7 @@ struct FillShape {
   static constexpr int TILE = WG * S;
   static constexpr int NWAVE = WG / 64;
   static constexpr int NWORD = S * O * NWAVE;  // one 64-bit ballot word per (s, o, wave)
-  static_assert(WG % 64 == 0 && NWORD <= 1024 && TILE * 16 <= 32768, "tile shape");
+  static_assert(WG % 64 == 0 && NWORD <= 1024 && TILE * 16 <= 40960, "tile shape");
 };
 
 // LDS of one workgroup.  CAP is the largest table it serves: up to
@@ -530,8 +530,9 @@ int launch_one(const FillArgs& args, hipStream_t st) {
 }
 
 // Launch of the variant with workgroup size wg and spl blocks per lane:
-// every shape of up to 2048 blocks per tile for plain fills, three for the
-// trace build.
+// every power-of-two shape of up to 2048 blocks per tile plus 256 x 10
+// (2560 blocks, about 60 slow normal outputs: one full wave for the drain)
+// for plain fills, three shapes for the trace build.
 template <uint32_t DIST, uint32_t DT, bool TRACE, bool ACCEL = false, bool TRAD = false, bool WIDE = false>
 int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
 #define ZIG_SHAPE(W, S_) \
@@ -539,7 +540,7 @@ int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
   if constexpr (!TRACE) {
     ZIG_SHAPE(64, 1) ZIG_SHAPE(64, 2) ZIG_SHAPE(64, 4) ZIG_SHAPE(64, 8)
     ZIG_SHAPE(128, 1) ZIG_SHAPE(128, 2) ZIG_SHAPE(128, 4) ZIG_SHAPE(128, 8)
-    ZIG_SHAPE(256, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4) ZIG_SHAPE(256, 8)
+    ZIG_SHAPE(256, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4) ZIG_SHAPE(256, 8) ZIG_SHAPE(256, 10)
     ZIG_SHAPE(512, 1) ZIG_SHAPE(512, 2) ZIG_SHAPE(512, 4)
     ZIG_SHAPE(1024, 1) ZIG_SHAPE(1024, 2)
   } else {

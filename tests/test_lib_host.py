@@ -109,6 +109,8 @@ def test_fill_argument_validation(zig):
         lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"i_max": 100}),
         lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 96}),
         lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 512, "spl": 8}),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 128, "spl": 10}),
+        lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"wg": 256, "spl": 12}),
         lambda: zig.zig_fill(0, 0, 1, 0, 10, 1.0, 1.0, fake, launch={"flags": 4}),
         # the traditional sampler: FP64 only, no trace, not with the accelerated variant, no moments
         lambda: zig.zig_fill(0, 1, 1, 0, 10, 1.0, 1.0, fake, launch={"flags": zig.LAUNCH_TRADITIONAL}),
