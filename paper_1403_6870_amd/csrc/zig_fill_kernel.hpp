@@ -216,16 +216,18 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
         OutT x;
         bool miss;  // the fast word does not decide the output
         if constexpr (DT == kF64) {
-          const uint64_t w =
-              (o == 0) ? ((uint64_t)c0 | ((uint64_t)c1 << 32)) : ((uint64_t)c2 | ((uint64_t)c3 << 32));
-          i = (uint32_t)w & imask;
-          x = (double)(w >> 11) * xs[i];
+          const uint32_t lo = (o == 0) ? c0 : c2, hi = (o == 0) ? c1 : c3;
+          i = lo & imask;
+          // the 53 magnitude bits k = hi 2^21 + (lo >> 11), converted
+          // exactly (k < 2^53) by one fma of the two 32-bit conversions
+          const double k = __builtin_fma((double)hi, 0x1p21, (double)(lo >> 11));
+          x = k * xs[i];
           if constexpr (TRAD)
-            miss = (w >> 11) >= c.tr.KQ[i];
+            miss = (((uint64_t)hi << 21) | (lo >> 11)) >= c.tr.KQ[i];
           else
             miss = i >= L;
           if constexpr (DIST == kDistNormal) {
-            if ((w >> 10) & 1u) x = -x;
+            if ((lo >> 10) & 1u) x = -x;
           }
         } else {
           const uint32_t w = (o == 0) ? c0 : (o == 1) ? c1 : (o == 2) ? c2 : c3;
