@@ -272,7 +272,8 @@ std::string build_host_trad(uint32_t dist, uint32_t n, HostTrad* out) {
   if (dist != kDistExp && dist != kDistNormal) return "unknown distribution";
   uint32_t b = 0;
   while (b < 31 && (1u << b) < n) ++b;
-  if ((1u << b) != n || n < 8 || n > kLdsLayers) return "the traditional sampler takes i_max a power of two in [8, 256]";
+  if ((1u << b) != n || n < 8 || n > kLdsLayers)
+    return "the traditional sampler takes i_max a power of two in [8, 256]";
   const Density P{dist};
   auto inverse = [&](q128 y) { return dist == kDistExp ? -logq(y) : sqrtq(-2 * logq(y)); };
   std::vector<q128> X(n), f(n);

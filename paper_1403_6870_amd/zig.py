@@ -152,9 +152,9 @@ _moments = _sig("zig_moments", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, 
 _last_error = _sig("zig_last_error", ctypes.c_char_p, [])
 _version = _sig("zig_version", ctypes.c_char_p, [])
 
-EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_get_trad_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill", "zig_fill_trace",
-           "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_moments", "zig_autotune", "zig_tuned_shape",
-           "zig_tuned_batch_shape", "zig_autotune_reset", "zig_server_now_ns", "zig_server_create",
+EXPORTS = ["zig_build_tables", "zig_get_tables", "zig_get_trad_tables", "zig_fill_exp", "zig_fill_normal", "zig_fill",
+           "zig_fill_trace", "zig_fill_batch", "zig_fill_batch_ex", "zig_fill_each", "zig_moments", "zig_autotune",
+           "zig_tuned_shape", "zig_tuned_batch_shape", "zig_autotune_reset", "zig_server_now_ns", "zig_server_create",
            "zig_server_submit", "zig_server_wait", "zig_server_release", "zig_server_drop_client",
            "zig_server_counters", "zig_server_set_counters", "zig_server_stats_get", "zig_server_replay",
            "zig_server_destroy", "zig_last_error", "zig_version"]
