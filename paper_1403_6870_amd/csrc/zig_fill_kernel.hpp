@@ -56,24 +56,37 @@ struct FillShape {
   static_assert(WG % 64 == 0 && NWORD <= 1024 && TILE * 16 <= 40960, "tile shape");
 };
 
-// LDS of one workgroup.  CAP is the largest table it serves: up to
-// kLdsLayers the slow-path tables (X, f, alias) are staged here too; wider
-// tables keep only the fast-path table here and the slow paths, which
-// serve a few outputs in a thousand, read the rest from device memory.
-template <uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers>
+// LDS of one workgroup.  CAP is the largest table it serves.  With SLOWLDS
+// the slow-path tables (X, f, alias) are staged here too; otherwise only
+// the fast-path table is, and the slow paths, which serve one or two
+// outputs in a hundred, read the rest from device memory (L2-resident).
+// Wide tables always run that way, and so do the shapes for which the
+// smaller footprint fits one more workgroup on a CU (lean_shape).
+// The traditional sampler (TRAD) keeps its quick-accept thresholds and
+// layer heights in T and f and has no use for X and A.
+template <uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers, bool SLOWLDS = (CAP <= kLdsLayers),
+          bool TRAD = false>
 struct FillLds {
   using Sh = FillShape<DT, WG, S>;
-  static constexpr uint32_t SLOW = CAP <= kLdsLayers ? CAP : 1;
+  static constexpr uint32_t SLOW_XA = SLOWLDS && !TRAD ? CAP : 1;
+  static constexpr uint32_t SLOW_FT = SLOWLDS || TRAD ? CAP : 1;
   typename Sh::OutT xs[CAP];
-  double X[SLOW + 1];
-  double f[SLOW + 1];
-  uint64_t T[SLOW];
-  uint32_t A[SLOW];
+  double X[SLOW_XA + 1];
+  double f[SLOW_FT + 1];
+  uint64_t T[SLOW_FT];
+  uint32_t A[SLOW_XA];
   typename Sh::VecT stage[Sh::TILE];
   uint64_t slowmap[Sh::NWORD];
   uint32_t prefix[Sh::NWORD + 1];
   uint32_t tile;
 };
+
+// 128 x 8 and 256 x 8 tiles: the staged slow tables (9 KB) are what keeps a
+// fourth (eighth) workgroup off a CU's 160 KB of LDS; without them the
+// normal fill runs at 4 instead of 3 waves per SIMD (2.40 -> 2.10 ms at
+// 2^30 FP64 on 256 x 8).  Larger workgroups of the same tile size are
+// limited by registers first and lose from the slower table reads.
+constexpr bool lean_shape(int wg, int s) { return (wg == 128 || wg == 256) && s == 8; }
 
 // Per-workgroup constants of one fill: table views, the fast-path table
 // (X_i 2^-53 as double for FP64, RN32(X_i) 2^-24/2^-23 as float for FP32),
@@ -94,8 +107,8 @@ struct TileLds {
   uint32_t* prefix;
 };
 
-template <uint32_t DIST, uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers>
-__device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG, S, CAP>& sh) {
+template <uint32_t DIST, uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers, bool SLOWLDS = (CAP <= kLdsLayers)>
+__device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG, S, CAP, SLOWLDS>& sh) {
   const DevTable* tb = a.tab;
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < CAP; i += WG) {
@@ -106,7 +119,7 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
   }
   FillCtx c;
   c.own = dev::global_view(tb);
-  if constexpr (CAP <= kLdsLayers) {
+  if constexpr (SLOWLDS) {
     for (uint32_t i = tid; i < CAP; i += WG) {
       sh.T[i] = tb->T[i];
       sh.A[i] = tb->A[i];
@@ -133,8 +146,9 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
 // The traditional sampler's context (FP64): widths W_i 2^-53 in the fast
 // table, quick-accept thresholds and layer heights in LDS, the exponential
 // tables of the normal tail read from device memory.
-template <uint32_t DIST, int WG, int S>
-__device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a, FillLds<kF64, WG, S>& sh) {
+template <uint32_t DIST, int WG, int S, bool SLOWLDS>
+__device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a,
+                                                    FillLds<kF64, WG, S, kLdsLayers, SLOWLDS, true>& sh) {
   const DevTrad* tb = a.ttab;
   for (uint32_t i = threadIdx.x; i < kLdsLayers; i += WG) {
     sh.xs[i] = tb->WS[i];
@@ -453,12 +467,14 @@ template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = fa
           bool WIDE = false>
 __global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
   static_assert(!(WIDE && (TRAD || ACCEL)), "wide tables: the plain modified sampler");
-  __shared__ FillLds<DT, WG, S, WIDE ? kMaxLayers : kLdsLayers> sh;
+  constexpr uint32_t CAP = WIDE ? kMaxLayers : kLdsLayers;
+  constexpr bool SLOWLDS = !WIDE && !lean_shape(WG, S);
+  __shared__ FillLds<DT, WG, S, CAP, SLOWLDS, TRAD> sh;
   const FillCtx c = [&] {
     if constexpr (TRAD)
-      return load_trad_tables<DIST, WG, S>(a, sh);
+      return load_trad_tables<DIST, WG, S, SLOWLDS>(a, sh);
     else
-      return load_tables<DIST, DT, WG, S, WIDE ? kMaxLayers : kLdsLayers>(a, sh);
+      return load_tables<DIST, DT, WG, S, CAP, SLOWLDS>(a, sh);
   }();
   TileLds tl;
   tl.stage = sh.stage;

@@ -29,8 +29,10 @@ constexpr int kMomS = 8;
 
 template <uint32_t DIST, uint32_t DT, bool ACCEL>
 __global__ void __launch_bounds__(kMomWG) moments_kernel(FillArgs a, double* tile_sums) {
-  __shared__ FillLds<DT, kMomWG, kMomS> sh;
-  const FillCtx c = load_tables<DIST, DT, kMomWG, kMomS>(a, sh);
+  // the slow-path tables stay in device memory, as in the fill's 256 x 8
+  // kernel: one more workgroup per CU
+  __shared__ FillLds<DT, kMomWG, kMomS, kLdsLayers, !lean_shape(kMomWG, kMomS)> sh;
+  const FillCtx c = load_tables<DIST, DT, kMomWG, kMomS, kLdsLayers, !lean_shape(kMomWG, kMomS)>(a, sh);
   TileLds tl;
   tl.stage = sh.stage;
   tl.slowmap = sh.slowmap;

@@ -60,10 +60,10 @@ uint32_t chunk_for(uint32_t wg, uint32_t spl, uint32_t step_blocks) {
 // Built-in table: the autotuner's choices on MI355X (256 CUs), as
 // {wg, spl, counter step in blocks} per [dist][dtype][size class].
 const uint32_t kBuiltin[2][2][kSizeClasses][3] = {
-    {{{512, 2, 16384}, {512, 4, 16384}, {512, 4, 32768}, {512, 4, 8192}},     // exp FP64
-     {{512, 1, 16384}, {1024, 2, 16384}, {1024, 2, 8192}, {512, 4, 16384}}},  // exp FP32
-    {{{512, 1, 16384}, {1024, 2, 16384}, {256, 8, 16384}, {256, 10, 8192}},   // normal FP64
-     {{256, 1, 16384}, {512, 4, 16384}, {512, 4, 16384}, {128, 8, 8192}}},    // normal FP32
+    {{{512, 2, 16384}, {512, 4, 16384}, {512, 4, 32768}, {256, 8, 8192}},     // exp FP64
+     {{512, 1, 16384}, {1024, 2, 16384}, {1024, 2, 8192}, {256, 8, 8192}}},   // exp FP32
+    {{{512, 1, 16384}, {1024, 2, 16384}, {256, 10, 8192}, {256, 8, 8192}},   // normal FP64
+     {{256, 1, 16384}, {512, 4, 16384}, {512, 4, 16384}, {256, 8, 8192}}},    // normal FP32
 };
 const uint32_t kBuiltinBatch[2] = {128, 8};
 
