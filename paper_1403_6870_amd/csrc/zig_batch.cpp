@@ -35,7 +35,7 @@ struct Slot {
   uint32_t cap = 0;           // requests the buffers hold
   hipEvent_t done = nullptr;  // last graph launch that read `host`
   bool used = false;
-  std::map<std::tuple<uint32_t, uint32_t, uint32_t>, hipGraphExec_t> graphs;  // (bucket, wg, spl)
+  std::map<std::tuple<uint32_t, uint32_t, uint32_t, bool>, hipGraphExec_t> graphs;  // (bucket, wg, spl, full)
 };
 
 struct DeviceBatch {
@@ -140,6 +140,8 @@ void make_descriptor(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t firs
 // About 8K blocks per counter step, and every resident workgroup gets a few
 // steps.  It travels in the header, so one graph serves every batch of a
 // size bucket; workgroups with no step to take leave at once.
+bool batch_full(uint64_t total_tiles, uint32_t lean_groups) { return total_tiles < 4ull * lean_groups; }
+
 uint32_t batch_chunk(uint64_t total_tiles, uint32_t tile_blocks, uint32_t groups) {
   uint64_t chunk = 8192 / tile_blocks;
   if (chunk < 1) chunk = 1;
@@ -186,8 +188,13 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   int r = device_tables_for(256, &tabs);
   if (r != ZIG_OK) return r;
   uint32_t groups = 0;
-  hipError_t e = (hipError_t)batch_groups(wg, spl, &groups);
+  hipError_t e = (hipError_t)batch_groups(wg, spl, false, &groups);
   if (e != hipSuccess) return hip_fail("batch occupancy", e);
+  const bool full = batch_full(total, groups);
+  if (full) {
+    e = (hipError_t)batch_groups(wg, spl, true, &groups);
+    if (e != hipSuccess) return hip_fail("batch occupancy", e);
+  }
 
   int dev = 0;
   e = hipGetDevice(&dev);
@@ -231,14 +238,14 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   if (flags & ZIG_BATCH_NO_GRAPH) {
     e = hipMemcpyAsync(s.dev, s.host, sizeof(BatchHeader) + (size_t)m * sizeof(BatchReq), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail("hipMemcpyAsync(batch)", e);
-    int le = launch_batch(wg, spl, grid, ba, stream);
+    int le = launch_batch(wg, spl, full, grid, ba, stream);
     if (le != 0) return hip_fail("batch launch", (hipError_t)le);
   } else {
     // the graph copies the bucket's worth of descriptors and launches the
     // device-filling grid
     uint32_t bucket = 64;
     while (bucket < m) bucket <<= 1;
-    const auto key = std::make_tuple(bucket, wg, spl);
+    const auto key = std::make_tuple(bucket, wg, spl, full);
     auto it = s.graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it != s.graphs.end()) {
@@ -253,7 +260,7 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
       if (e != hipSuccess) return hip_fail("hipStreamBeginCapture", e);
       const size_t bytes = sizeof(BatchHeader) + (size_t)bucket * sizeof(BatchReq);
       hipError_t e1 = hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, db->capture);
-      int le = launch_batch(wg, spl, grid, ba, db->capture);
+      int le = launch_batch(wg, spl, full, grid, ba, db->capture);
       e = hipStreamEndCapture(db->capture, &g);
       if (e1 != hipSuccess) return hip_fail("capture: hipMemcpyAsync", e1);
       if (le != 0) return hip_fail("capture: batch launch", (hipError_t)le);

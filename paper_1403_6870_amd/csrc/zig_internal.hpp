@@ -176,9 +176,15 @@ uint32_t batch_chunk(uint64_t total_tiles, uint32_t tile_blocks, uint32_t groups
 // Batch kernel launch of one (wg, spl) variant with `grid` workgroups
 // (zig_batch.hip); returns 0 or a hipError_t value.  batch_groups gives the
 // resident workgroup count of that variant on the current device.
-int launch_batch(uint32_t wg, uint32_t spl, uint32_t grid, const BatchArgs& a, void* stream);
+// `full` selects the variant that stages every table in LDS (see
+// batch_full); batch_groups gives each variant's resident count.
+int launch_batch(uint32_t wg, uint32_t spl, bool full, uint32_t grid, const BatchArgs& a, void* stream);
 
-int batch_groups(uint32_t wg, uint32_t spl, uint32_t* groups);
+int batch_groups(uint32_t wg, uint32_t spl, bool full, uint32_t* groups);
+
+// The staged-table variant for batches too small to keep the lean one's
+// resident workgroups busy for a few tiles each (zig_batch.cpp).
+bool batch_full(uint64_t total_tiles, uint32_t lean_groups);
 bool batch_shape_supported(uint32_t wg, uint32_t spl);
 
 // Shared helpers of the C ABI implementation (zig_api.cpp).

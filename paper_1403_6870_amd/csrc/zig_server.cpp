@@ -185,7 +185,7 @@ struct Server {
   uint64_t* counters_dev = nullptr;
   std::vector<hipStream_t> fill_streams;
   const DevTable* tabs = nullptr;
-  uint32_t wg = 256, spl = 4, groups = 0;
+  uint32_t wg = 256, spl = 4, groups = 0, groups_full = 0;  // resident workgroups: lean and staged-table kernels
   // host fake backend
   std::vector<char> arena_host;
   uint64_t fake_seen = 0;
@@ -255,7 +255,9 @@ int launch_device(Server* s, Batch* b) {
   std::memset(h, 0, sizeof(*h));
   h->count = m;
   h->total_tiles = (uint32_t)total;
-  h->chunk = batch_chunk(total, tile_blocks, s->groups);
+  const bool full = batch_full(total, s->groups);
+  const uint32_t groups = full ? s->groups_full : s->groups;
+  h->chunk = batch_chunk(total, tile_blocks, groups);
   hipStream_t fs = s->fill_streams[b->stream];
   hipError_t e = hipMemcpyAsync(d.desc_dev, d.desc_host, sizeof(BatchHeader) + (size_t)m * sizeof(BatchReq),
                                 hipMemcpyHostToDevice, fs);
@@ -266,7 +268,11 @@ int launch_device(Server* s, Batch* b) {
   ba.counters = d.tile_counters;
   ba.client_next = s->counters_dev;
   ba.seed_base = s->cfg.seed_base;
-  const int le = launch_batch(s->wg, s->spl, s->groups, ba, fs);
+  // no more workgroups than counter steps: a small batch then dispatches
+  // (and retires) a few workgroups instead of every resident one
+  const uint64_t steps = (total + h->chunk - 1) / h->chunk;
+  const uint32_t grid = steps < (uint64_t)groups ? (uint32_t)steps : groups;
+  const int le = launch_batch(s->wg, s->spl, full, grid, ba, fs);
   if (le != 0) return fail(ZIG_EHIP, std::string("serve: batch launch: ") + hipGetErrorString((hipError_t)le));
   for (const Item& it : b->items) {
     if (!it.copy_to) continue;
@@ -527,7 +533,8 @@ int setup_device(Server* s) {
   const int r = device_tables_for(256, &s->tabs);
   if (r != ZIG_OK) return r;
   tuned_batch_shape(&s->wg, &s->spl);
-  ZIG_CK((hipError_t)batch_groups(s->wg, s->spl, &s->groups), "batch occupancy");
+  ZIG_CK((hipError_t)batch_groups(s->wg, s->spl, false, &s->groups), "batch occupancy");
+  ZIG_CK((hipError_t)batch_groups(s->wg, s->spl, true, &s->groups_full), "batch occupancy");
   if (s->cfg.arena) {
     s->arena_dev = static_cast<char*>(s->cfg.arena);
   } else {
