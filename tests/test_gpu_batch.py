@@ -89,6 +89,21 @@ def test_batch_equals_single_fills(O, env, graph):
 
 
 @pytest.mark.parametrize("wg,spl", BATCH_SHAPES)
+def test_large_batch_lean_layout(env, wg, spl):
+    """A batch of about 5e7 outputs: many tiles per resident workgroup at
+    every shape, so the kernel reads the slow-path tables from device
+    memory (the small batches above run the layout that stages them in
+    LDS); outputs bit-identical to single fills."""
+    torch, zig = env
+    rng = np.random.default_rng(100 + wg + spl)
+    reqs = mixed_requests(rng, 200, 22)
+    assert sum(r[4] for r in reqs) > 4 * 10 ** 7
+    want = _single(torch, zig, reqs)
+    got = _batch(torch, zig, reqs, {"wg": wg, "spl": spl})
+    assert _same(got, want)
+
+
+@pytest.mark.parametrize("wg,spl", BATCH_SHAPES)
 def test_batch_shapes(env, wg, spl):
     torch, zig = env
     rng = np.random.default_rng(wg * 10 + spl)
