@@ -154,9 +154,9 @@ int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dt
 /* Launch shape, table size and variant for zig_fill.  Zero fields mean
  * "pick": i_max 256; wg/spl from the tuned table.  wg in {64,...,1024}
  * lanes per workgroup and spl in {1,2,4,8} Philox blocks per lane make a
- * tile of wg * spl blocks (at most 2048; also wg 256 with spl 10, 2560
- * blocks), which is also the depth of the per-workgroup slow-output
- * queue.
+ * tile of wg * spl blocks (at most 2048; also wg 256 with spl 7 or 10,
+ * 1792 or 2560 blocks), which is also the depth of the per-workgroup
+ * slow-output queue.
  * i_max above 256 (512 or 1024 layers) takes b = log2 i_max index bits:
  * the FP64 word keeps its layout (sign bit 10, magnitude bits 11..63);
  * the FP32 word gives bits 0..b-1 to the index, the exponential's

@@ -81,12 +81,21 @@ struct FillLds {
   uint32_t tile;
 };
 
-// 128 x 8 and 256 x 8 tiles: the staged slow tables (9 KB) are what keeps a
-// fourth (eighth) workgroup off a CU's 160 KB of LDS; without them the
-// normal fill runs at 4 instead of 3 waves per SIMD (2.40 -> 2.10 ms at
-// 2^30 FP64 on 256 x 8).  Larger workgroups of the same tile size are
-// limited by registers first and lose from the slower table reads.
-constexpr bool lean_shape(int wg, int s) { return (wg == 128 || wg == 256) && s == 8; }
+// 128 x 8, 256 x 8 and 256 x 7 tiles: the staged slow tables (9 KB) are
+// what keeps a fourth (256 x 7: fifth) workgroup off a CU's 160 KB of LDS;
+// without them the normal fill runs at 4 instead of 3 waves per SIMD
+// (2.40 -> 2.10 ms at 2^30 FP64 on 256 x 8).  Larger workgroups of the
+// same tile size are limited by registers first and lose from the slower
+// table reads.
+constexpr bool lean_shape(int wg, int s) {
+  return ((wg == 128 || wg == 256) && s == 8) || (wg == 256 && s == 7);
+}
+
+// Waves per SIMD the register allocator is asked to allow: 256 x 7 fits 5
+// workgroups in LDS, and the normal kernel, at 103 registers by default,
+// fits 5 waves in 87 without spilling when asked (2.10 -> 2.06 ms for the
+// normal 2^30 FP64 fill, 1.37 -> 1.32 ms in FP32).  1 means no request.
+constexpr int waves_hint(int wg, int s, bool plain) { return plain && wg == 256 && s == 7 ? 5 : 1; }
 
 // Per-workgroup constants of one fill: table views, the fast-path table
 // (X_i 2^-53 as double for FP64, RN32(X_i) 2^-24/2^-23 as float for FP32),
@@ -465,7 +474,8 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
 // resets the counters for the next launch on the same stream.
 template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
           bool WIDE = false>
-__global__ void __launch_bounds__(WG) fill_kernel(FillArgs a) {
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(waves_hint(WG, S, !TRAD && !WIDE))))
+fill_kernel(FillArgs a) {
   static_assert(!(WIDE && (TRAD || ACCEL)), "wide tables: the plain modified sampler");
   constexpr uint32_t CAP = WIDE ? kMaxLayers : kLdsLayers;
   constexpr bool SLOWLDS = !WIDE && !lean_shape(WG, S);
@@ -548,9 +558,10 @@ int launch_one(const FillArgs& args, hipStream_t st) {
 }
 
 // Launch of the variant with workgroup size wg and spl blocks per lane:
-// every power-of-two shape of up to 2048 blocks per tile plus 256 x 10
-// (2560 blocks, about 60 slow normal outputs: one full wave for the drain)
-// for plain fills, three shapes for the trace build.
+// every power-of-two shape of up to 2048 blocks per tile plus 256 x 7
+// (1792 blocks, 5 waves per SIMD) and 256 x 10 (2560 blocks, about 60 slow
+// normal outputs: one full wave for the drain) for plain fills, three
+// shapes for the trace build.
 template <uint32_t DIST, uint32_t DT, bool TRACE, bool ACCEL = false, bool TRAD = false, bool WIDE = false>
 int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
 #define ZIG_SHAPE(W, S_) \
@@ -558,7 +569,7 @@ int launch_shape(uint32_t wg, uint32_t spl, const FillArgs& a, hipStream_t st) {
   if constexpr (!TRACE) {
     ZIG_SHAPE(64, 1) ZIG_SHAPE(64, 2) ZIG_SHAPE(64, 4) ZIG_SHAPE(64, 8)
     ZIG_SHAPE(128, 1) ZIG_SHAPE(128, 2) ZIG_SHAPE(128, 4) ZIG_SHAPE(128, 8)
-    ZIG_SHAPE(256, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4) ZIG_SHAPE(256, 8) ZIG_SHAPE(256, 10)
+    ZIG_SHAPE(256, 1) ZIG_SHAPE(256, 2) ZIG_SHAPE(256, 4) ZIG_SHAPE(256, 7) ZIG_SHAPE(256, 8) ZIG_SHAPE(256, 10)
     ZIG_SHAPE(512, 1) ZIG_SHAPE(512, 2) ZIG_SHAPE(512, 4)
     ZIG_SHAPE(1024, 1) ZIG_SHAPE(1024, 2)
   } else {

@@ -60,10 +60,10 @@ uint32_t chunk_for(uint32_t wg, uint32_t spl, uint32_t step_blocks) {
 // Built-in table: the autotuner's choices on MI355X (256 CUs), as
 // {wg, spl, counter step in blocks} per [dist][dtype][size class].
 const uint32_t kBuiltin[2][2][kSizeClasses][3] = {
-    {{{512, 2, 16384}, {512, 4, 16384}, {512, 4, 32768}, {256, 8, 8192}},     // exp FP64
-     {{512, 1, 16384}, {1024, 2, 16384}, {1024, 2, 8192}, {256, 8, 8192}}},   // exp FP32
-    {{{512, 1, 16384}, {1024, 2, 16384}, {256, 10, 8192}, {256, 8, 8192}},   // normal FP64
-     {{256, 1, 16384}, {512, 4, 16384}, {512, 4, 16384}, {256, 8, 8192}}},    // normal FP32
+    {{{512, 2, 16384}, {512, 4, 16384}, {512, 4, 32768}, {256, 7, 8192}},     // exp FP64
+     {{512, 1, 16384}, {1024, 2, 16384}, {1024, 2, 8192}, {256, 7, 16384}}},  // exp FP32
+    {{{512, 1, 16384}, {1024, 2, 16384}, {256, 10, 8192}, {256, 7, 8192}},    // normal FP64
+     {{256, 1, 16384}, {512, 4, 16384}, {256, 10, 8192}, {256, 7, 8192}}},    // normal FP32
 };
 const uint32_t kBuiltinBatch[2] = {128, 8};
 
@@ -247,7 +247,7 @@ int measure(Table* t) {
   }
   int r = ZIG_OK;
   const uint32_t wgs[] = {64, 128, 256, 512, 1024};
-  const uint32_t spls[] = {1, 2, 4, 8, 10};
+  const uint32_t spls[] = {1, 2, 4, 7, 8, 10};
   for (uint32_t d = 0; d < 2 && r == ZIG_OK; ++d)
     for (uint32_t dt = 0; dt < 2 && r == ZIG_OK; ++dt)
       for (uint32_t c = 0; c < kSizeClasses && r == ZIG_OK; ++c) {
@@ -354,7 +354,7 @@ int measure(Table* t) {
 }  // namespace
 
 bool shape_supported(uint32_t wg, uint32_t spl) {
-  if (wg == 256 && spl == 10) return true;
+  if (wg == 256 && (spl == 7 || spl == 10)) return true;
   const bool w = wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024;
   const bool s = spl == 1 || spl == 2 || spl == 4 || spl == 8;
   return w && s && wg * spl <= 2048;

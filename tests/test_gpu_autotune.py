@@ -12,7 +12,7 @@ from helpers import EXP, F32, F64, NORMAL
 
 pytestmark = pytest.mark.gpu
 
-FILL_SHAPES = {(w, s) for w in (64, 128, 256, 512, 1024) for s in (1, 2, 4, 8) if w * s <= 2048} | {(256, 10)}
+FILL_SHAPES = {(w, s) for w in (64, 128, 256, 512, 1024) for s in (1, 2, 4, 8) if w * s <= 2048} | {(256, 7), (256, 10)}
 BATCH_SHAPES = {(64, 4), (128, 4), (128, 8), (256, 2), (256, 4), (512, 2)}
 
 
