@@ -140,8 +140,6 @@ void make_descriptor(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t firs
 // About 8K blocks per counter step, and every resident workgroup gets a few
 // steps.  It travels in the header, so one graph serves every batch of a
 // size bucket; workgroups with no step to take leave at once.
-bool batch_full(uint64_t total_tiles, uint32_t lean_groups) { return total_tiles < 4ull * lean_groups; }
-
 uint32_t batch_chunk(uint64_t total_tiles, uint32_t tile_blocks, uint32_t groups) {
   uint64_t chunk = 8192 / tile_blocks;
   if (chunk < 1) chunk = 1;
@@ -149,6 +147,11 @@ uint32_t batch_chunk(uint64_t total_tiles, uint32_t tile_blocks, uint32_t groups
   if (chunk > cap_chunk) chunk = cap_chunk < 1 ? 1 : cap_chunk;
   return (uint32_t)chunk;
 }
+
+// Fewer than four tiles per resident workgroup of the lean kernel: the
+// batch is over before its tables would warm in L2, so the kernel that
+// stages them in LDS is the faster one.
+bool batch_full(uint64_t total_tiles, uint32_t lean_groups) { return total_tiles < 4ull * lean_groups; }
 
 int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const zig_batch_opts* opts) {
   clear_error();

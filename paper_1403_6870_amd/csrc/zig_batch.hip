@@ -231,9 +231,11 @@ bool batch_shape_supported(uint32_t wg, uint32_t spl) {
 }
 
 int batch_groups(uint32_t wg, uint32_t spl, bool full, uint32_t* groups) {
-#define ZIG_B(W, S_)                                                                       \
-  if (wg == W && spl == S_)                                                                \
-    return full ? groups_of(batch_kernel<W, S_, true>, W, groups) : groups_of(batch_kernel<W, S_, false>, W, groups);
+#define ZIG_B(W, S_)                                                     \
+  if (wg == W && spl == S_) {                                            \
+    if (full) return groups_of(batch_kernel<W, S_, true>, W, groups);    \
+    return groups_of(batch_kernel<W, S_, false>, W, groups);             \
+  }
   ZIG_BATCH_SHAPES(ZIG_B)
 #undef ZIG_B
   return (int)hipErrorInvalidConfiguration;

@@ -13,7 +13,8 @@ from helpers import EXP, F32, F64, NORMAL, gpu_fill, oracle_fill, parity, to_np
 pytestmark = pytest.mark.gpu
 
 ULP = {F64: 4, F32: 2}
-ZIG_LAUNCH_SHAPES = [(w, s) for w in (64, 128, 256, 512, 1024) for s in (1, 2, 4, 8) if w * s <= 2048] + [(256, 7), (256, 10)]
+ZIG_LAUNCH_SHAPES = ([(w, s) for w in (64, 128, 256, 512, 1024) for s in (1, 2, 4, 8) if w * s <= 2048]
+                     + [(256, 7), (256, 10)])
 
 
 @pytest.fixture(scope="module")
