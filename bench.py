@@ -366,7 +366,7 @@ def autotune_report(zig):
 
 
 def cpu_baseline():
-    """The oracle on the host cores, about 10 s of work: the first 2^31
+    """The oracle on the host cores, about 10-15 s of work: the first 2^32
     outputs of each headline stream on all threads (in chunks of 2^26, so
     host memory stays small), and the first 2^26 of each on one thread."""
     from oracle import oracle
@@ -380,12 +380,12 @@ def cpu_baseline():
             oracle.fill(1, 0, 12, first, chunk, 3.0, -1.0, threads=nthreads)
         return time.perf_counter() - t0
 
-    n_all, n_one = 1 << 31, 1 << 26  # per distribution
+    n_all, n_one = 1 << 32, 1 << 26  # per distribution
     t_all = run(n_all, threads)
     t_one = run(n_one, 1)
     return {
         "value": round(2 * n_all / t_all / 1e9, 5), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
-        "sample": "2^31 Exp(2.5) + 2^31 N(-1,3) FP64 outputs (indices 0..2^31-1 of the benchmark streams, "
+        "sample": "2^32 Exp(2.5) + 2^32 N(-1,3) FP64 outputs (indices 0..2^32-1 of the benchmark streams, "
                   "chunks of 2^26), %d threads over contiguous index ranges, %.1f s" % (threads, t_all),
         "single_thread": {"value": round(2 * n_one / t_one / 1e9, 5), "unit": "Gsamples/s",
                           "sample": "2^26 + 2^26 FP64 outputs, 1 thread, %.1f s" % t_one},
