@@ -367,6 +367,19 @@ __device__ __forceinline__ double trad_slow(const TradView& own, const TradView&
   return x;
 }
 
+// -x when bit 31 of `bit` is set, else x: the bit xored into the sign
+// (one three-input bitop, truth table of S0 ^ (S1 & S2), instead of a
+// compare and select); -0.0 for x = +0.0, as negation gives.
+__device__ __forceinline__ double with_sign_of(double x, uint32_t bit) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), bit, 0x80000000u, 0x78);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint32_t)b);
+}
+__device__ __forceinline__ float with_sign_of(float x, uint32_t bit) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, x);
+  return __builtin_bit_cast(float, __builtin_amdgcn_bitop3_b32(b, bit, 0x80000000u, 0x78));
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }

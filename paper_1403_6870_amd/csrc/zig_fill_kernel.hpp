@@ -212,7 +212,12 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   const uint32_t L = TRAD ? 0u : c.own.L;
   const uint32_t imask = TRAD ? c.tr.imask : c.own.imask;
   const uint32_t s32 = WIDE ? (c.own.b > 8u ? c.own.b : 8u) : 8u;
-  const float fscale = (float)c.scale, fshift = (float)c.shift;
+  const float fscale = (float)c.scale;
+  // the location sits in VGPRs for the whole tile: a VALU fma takes only
+  // one scalar operand, and rematerialising it cost a move per output
+  double shiftv = c.shift;
+  float fshift = (float)c.shift;
+  if constexpr (DIST == kDistNormal) asm volatile("" : "+v"(shiftv), "+v"(fshift));
   OutT* const out = static_cast<OutT*>(a.out);
   VecT* const stage = static_cast<VecT*>(sh.stage);
   OutT* const stage_s = static_cast<OutT*>(sh.stage);
@@ -249,9 +254,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
             miss = (((uint64_t)hi << 21) | (lo >> 11)) >= c.tr.KQ[i];
           else
             miss = i >= L;
-          if constexpr (DIST == kDistNormal) {
-            if ((lo >> 10) & 1u) x = -x;
-          }
+          if constexpr (DIST == kDistNormal) x = dev::with_sign_of(x, lo << 21);
         } else {
           const uint32_t w = (o == 0) ? c0 : (o == 1) ? c1 : (o == 2) ? c2 : c3;
           i = w & imask;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
             x = (float)(w >> s32) * xs[i];
           } else {
             x = (float)(w >> (s32 + 1u)) * xs[i];
-            if ((w >> s32) & 1u) x = -x;
+            x = dev::with_sign_of(x, w << (31u - s32));
           }
         }
         // a slow output's value here is a placeholder that phase B replaces;
@@ -274,7 +277,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
             v[o] = fscale * x;
         } else {
           if constexpr (DT == kF64)
-            v[o] = __builtin_fma(c.scale, x, c.shift);
+            v[o] = __builtin_fma(c.scale, x, shiftv);
           else
             v[o] = __builtin_fmaf(fscale, x, fshift);
         }
