@@ -445,7 +445,18 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
     return;
   }
 
-  // C: staging tile to HBM
+  // C: staging tile to HBM.  An interior tile with 16-byte aligned blocks
+  // (the common case) stores from one uniform base pointer at lane offsets.
+  if (interior && a.aligned16) {
+    VecT* const dst = reinterpret_cast<VecT*>(out + (tile0 * O - a.first));
+    // formed per tile, so the compiler does not keep one offset register
+    // per slice alive across the whole persistent loop
+    uint32_t lane_blk = tid;
+    asm volatile("" : "+v"(lane_blk));
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s * WG + lane_blk] = stage[s * WG + tid];
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;

@@ -63,7 +63,7 @@ const uint32_t kBuiltin[2][2][kSizeClasses][3] = {
     {{{512, 2, 16384}, {512, 4, 16384}, {512, 4, 32768}, {256, 7, 8192}},     // exp FP64
      {{512, 1, 16384}, {1024, 2, 16384}, {1024, 2, 8192}, {256, 7, 16384}}},  // exp FP32
     {{{512, 1, 16384}, {1024, 2, 16384}, {256, 10, 8192}, {256, 7, 8192}},    // normal FP64
-     {{256, 1, 16384}, {512, 4, 16384}, {256, 10, 8192}, {256, 7, 8192}}},    // normal FP32
+     {{256, 1, 16384}, {512, 4, 16384}, {256, 10, 8192}, {128, 8, 8192}}},    // normal FP32
 };
 const uint32_t kBuiltinBatch[2] = {128, 8};
 
