@@ -380,6 +380,32 @@ __device__ __forceinline__ float with_sign_of(float x, uint32_t bit) {
   return __builtin_bit_cast(float, __builtin_amdgcn_bitop3_b32(b, bit, 0x80000000u, 0x78));
 }
 
+// Byte address in LDS of a pointer into shared memory.
+template <class T>
+__device__ __forceinline__ uint32_t lds_address(T* p) {
+  return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) T*)p;
+}
+
+// Stores the wave-uniform v (a scalar register pair, such as a ballot) at
+// LDS address addr + off from lane 0 alone: exec is set to that lane, v is
+// moved into its vector registers and stored, and exec is restored, all in
+// one block.  addr must hold the address in lane 0 (computed in uniform
+// code); off must fold to a constant.  Written out because the compiler
+// otherwise keeps a lane-0 exec mask for the whole kernel and, short of
+// scalar registers, reloads it from a vector register twice per store.
+__device__ __forceinline__ void store_from_lane0(uint32_t addr, uint64_t v, int off) {
+  uint64_t saved, vd;
+  asm volatile(
+      "s_mov_b64 %0, exec\n\t"
+      "s_mov_b64 exec, 1\n\t"
+      "v_mov_b64 %1, %3\n\t"
+      "ds_write_b64 %2, %1 offset:%4\n\t"
+      "s_mov_b64 exec, %0"
+      : "=&s"(saved), "=&v"(vd)
+      : "v"(addr), "s"(v), "i"(off)
+      : "memory");
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }

@@ -226,6 +226,8 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   const uint64_t tile0 = a.blk0 + (uint64_t)t * TILE;
   const bool interior = a.has_full && tile0 >= a.full_lo && tile0 + (TILE - 1) <= a.full_hi;
 
+  // this wave's first bitmap word, as an LDS address
+  const uint32_t lds_word = dev::lds_address(sh.slowmap + wave);
   // A: fast path into the staging tile, slow outputs into the bitmap
   auto phase_a = [&](auto interior_tag) {
     constexpr bool IN = decltype(interior_tag)::value;
@@ -282,7 +284,12 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
             v[o] = __builtin_fmaf(fscale, x, fshift);
         }
         const uint64_t mask = __builtin_amdgcn_ballot_w64(slow);
-        if (lane == 0) sh.slowmap[(s * O + o) * NWAVE + wave] = mask;
+        // the normal kernels run out of scalar registers, and the
+        // compiler's lane-0 store then reloads its exec mask per output
+        if constexpr (DIST == kDistNormal)
+          dev::store_from_lane0(lds_word, mask, (s * O + o) * NWAVE * 8);
+        else if (lane == 0)
+          sh.slowmap[(s * O + o) * NWAVE + wave] = mask;
         if constexpr (TRACE) {
           if (live) {
             const uint64_t k = g - a.first;
