@@ -86,8 +86,11 @@ def lib():
         L.orc_sample_region.restype = i32
         L.orc_alias_draw.argtypes = [tp, u64]
         L.orc_alias_draw.restype = u32
-        L.orc_moments.argtypes = [i32, i32, tp, tp, u64, u64, u64, dbl, dbl, ctypes.POINTER(dbl), i32]
+        L.orc_moments.argtypes = [i32, i32, tp, tp, u64, u64, u64, dbl, dbl, ctypes.POINTER(dbl),
+                                  ctypes.POINTER(dbl), i32]
         L.orc_moments.restype = i32
+        L.orc_exact_sum.argtypes = [vp, u64, ctypes.POINTER(dbl)]
+        L.orc_exact_sum.restype = i32
         trp = ctypes.POINTER(Trad)
         L.orc_build_trad.argtypes = [i32, u32, trp]
         L.orc_build_trad.restype = i32
@@ -199,14 +202,25 @@ def fill(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256, ac
     return out
 
 
-def moments(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256, accel=False):
-    """Raw moment sums (S1..S5) of the outputs of the same fill, in the
-    fixed summation order of orc_moments."""
+def moments(dist, dtype, seed, first, n, scale, shift=0.0, threads=1, i_max=256, accel=False, with_abs=False):
+    """Raw moment sums (S1..S5) of the outputs of the same fill, each the
+    exact sum rounded once; with_abs=True also returns the sums of |x^p|."""
     out = (ctypes.c_double * 5)()
+    absd = (ctypes.c_double * 5)()
     ex, nt = _tabs(dist, i_max, accel)
-    if lib().orc_moments(dist, dtype, ex, nt, seed, first, n, scale, shift, out, threads) != 0:
+    if lib().orc_moments(dist, dtype, ex, nt, seed, first, n, scale, shift, out, absd, threads) != 0:
         raise ValueError("orc_moments rejected its arguments")
-    return np.array(list(out))
+    s = np.array(list(out))
+    return (s, np.array(list(absd))) if with_abs else s
+
+
+def exact_sum(x):
+    """The exact sum of the doubles in x, rounded once to double."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    s = ctypes.c_double()
+    if lib().orc_exact_sum(a.ctypes.data if a.size else None, a.size, ctypes.byref(s)) != 0:
+        raise ValueError("orc_exact_sum rejected its arguments")
+    return s.value
 
 
 def fill_trace(dist, dtype, seed, first, n, scale, shift=0.0, i_max=256, accel=False):

@@ -701,90 +701,176 @@ int orc_fill(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, ui
   return 0;
 }
 
-/* ---- raw moments in a fixed summation order ----------------------------
- * The sums S_p = sum over outputs of x^p, p = 1..5, of the outputs a fill
- * of (dist, dtype, seed, first, n, scale, shift) would write, each x taken
- * as written (double, or float widened to double) and its powers formed as
- * q1 = x, q2 = x*x, q3 = q2*x, q4 = q2*q2, q5 = q4*x.  The order of the
- * additions is part of the definition, so that any implementation of it
- * gets the same bits:
- *   - blocks of `per` outputs (2 for FP64, 4 for FP32), numbered from
- *     blk0 = first / per; tiles of 2048 blocks from blk0;
- *   - in a tile, lane l (0..255) adds, from +0, the powers of the outputs of
- *     blocks l, l + 256, ..., l + 7*256 of the tile, each block's outputs in
- *     order, skipping outputs outside [first, first + n - 1];
- *   - the 256 lane sums are reduced by halving: for s = 128, 64, ..., 1,
- *     v[l] = v[l] + v[l + s] for l < s; the tile sum is v[0];
- *   - groups of 256 consecutive tiles (the last one padded with +0) are
- *     reduced the same way;
- *   - the total is +0 plus the group sums, one after the other in order. */
-#define MOM_TILE_BLOCKS 2048u
-#define MOM_LANES 256u
+/* ---- raw moments (Appendix B's test statistic; section 3's
+ * generate-and-aggregate benchmark) -------------------------------------
+ * S_p = sum of x^p, p = 1..5, over the outputs x of a fill of (dist,
+ * dtype, seed, first, n, scale, shift), each x taken as the fill writes
+ * it (a float widened to double) and its powers formed by double
+ * multiplications q2 = x*x, q3 = q2*x, q4 = q2*q2, q5 = q4*x.  The sum is
+ * the exact sum of those terms rounded once to double (to nearest, ties
+ * to even), so it depends on no order of addition; the absolute sums
+ * sum |q_p| are formed the same way (they bound any other order's
+ * rounding error). */
 
-static void halving_sum(double v[][5], uint32_t width) {
-  for (uint32_t s = width / 2; s >= 1; s /= 2)
-    for (uint32_t l = 0; l < s; ++l)
-      for (int p = 0; p < 5; ++p) v[l][p] = v[l][p] + v[l + s][p];
+/* Exact sum of doubles.  A finite double is m 2^(e - 1075) with m an
+ * integer below 2^53 and e its biased exponent field (a subnormal counts
+ * as e = 1 without the hidden bit).  Bucket e holds the signed sum of the
+ * m of all terms with that field, so the sum is sum_e bucket[e] 2^(e-1075)
+ * exactly; a 128-bit bucket takes 2^74 terms before it could overflow. */
+#define XS_BUCKETS 2047
+typedef struct {
+  __int128 b[XS_BUCKETS];
+  int nonfinite;
+} exact_sum;
+
+static void xs_add(exact_sum* s, double x) {
+  uint64_t u;
+  memcpy(&u, &x, sizeof(u));
+  uint32_t e = (uint32_t)(u >> 52) & 0x7ffu;
+  int64_t m = (int64_t)(u & ((1ull << 52) - 1));
+  if (e == 0x7ffu) {
+    s->nonfinite = 1;
+    return;
+  }
+  if (e == 0)
+    e = 1;
+  else
+    m |= (int64_t)1 << 52;
+  if (u >> 63)
+    s->b[e] -= m;
+  else
+    s->b[e] += m;
+}
+
+static void xs_merge(exact_sum* into, const exact_sum* from) {
+  for (int e = 0; e < XS_BUCKETS; ++e) into->b[e] += from->b[e];
+  into->nonfinite |= from->nonfinite;
+}
+
+/* Unsigned big integers of XS_LIMBS 64-bit limbs, least significant
+ * first, counting units of 2^-1074: bucket e weighs 2^(e-1). */
+#define XS_LIMBS 36
+
+static void big_add_shifted(uint64_t* big, unsigned __int128 v, uint32_t sh) {
+  const uint32_t q = sh / 64, r = sh % 64;
+  const uint64_t v0 = (uint64_t)v, v1 = (uint64_t)(v >> 64);
+  uint64_t w[3];
+  w[0] = v0 << r;
+  w[1] = r ? (v1 << r) | (v0 >> (64 - r)) : v1;
+  w[2] = r ? v1 >> (64 - r) : 0;
+  unsigned __int128 carry = 0;
+  for (uint32_t k = q; k < XS_LIMBS; ++k) {
+    const unsigned __int128 t = (unsigned __int128)big[k] + (k - q < 3 ? w[k - q] : 0) + carry;
+    big[k] = (uint64_t)t;
+    carry = t >> 64;
+    if (k - q >= 2 && carry == 0) break;
+  }
+}
+
+static int big_cmp(const uint64_t* a, const uint64_t* b) {
+  for (int k = XS_LIMBS - 1; k >= 0; --k)
+    if (a[k] != b[k]) return a[k] < b[k] ? -1 : 1;
+  return 0;
+}
+
+static void big_sub(uint64_t* a, const uint64_t* b) { /* a -= b, a >= b */
+  uint64_t borrow = 0;
+  for (int k = 0; k < XS_LIMBS; ++k) {
+    const uint64_t bk = b[k] + borrow;
+    const uint64_t nb = (bk < borrow) || (a[k] < bk);
+    a[k] -= bk;
+    borrow = nb;
+  }
+}
+
+static int big_bit(const uint64_t* a, int pos) { return (int)((a[pos / 64] >> (pos % 64)) & 1u); }
+
+/* The exact sum rounded to double, to nearest with ties to even (an
+ * exact zero gives +0; a non-finite term gives NaN). */
+static double xs_round(const exact_sum* s) {
+  if (s->nonfinite) return NAN;
+  uint64_t pos[XS_LIMBS], neg[XS_LIMBS];
+  memset(pos, 0, sizeof(pos));
+  memset(neg, 0, sizeof(neg));
+  for (uint32_t e = 1; e < XS_BUCKETS; ++e) {
+    const __int128 v = s->b[e];
+    if (v > 0) big_add_shifted(pos, (unsigned __int128)v, e - 1);
+    if (v < 0) big_add_shifted(neg, (unsigned __int128)0 - (unsigned __int128)v, e - 1);
+  }
+  double sign = 1.0;
+  const int c = big_cmp(pos, neg);
+  if (c == 0) return 0.0;
+  if (c > 0) {
+    big_sub(pos, neg);
+  } else {
+    big_sub(neg, pos);
+    memcpy(pos, neg, sizeof(pos));
+    sign = -1.0;
+  }
+  int top = XS_LIMBS * 64 - 1;
+  while (!big_bit(pos, top)) --top;
+  if (top < 53) return sign * ldexp((double)pos[0], -1074); /* exact */
+  uint64_t mant = 0;
+  for (int k = top; k > top - 53; --k) mant = (mant << 1) | (uint64_t)big_bit(pos, k);
+  const int rbit = big_bit(pos, top - 53);
+  int sticky = 0;
+  for (int k = top - 54; k >= 0 && !sticky; --k) {
+    if (k % 64 == 63 && pos[k / 64] == 0) {
+      k -= 63;
+      continue;
+    }
+    sticky = big_bit(pos, k);
+  }
+  if (rbit && (sticky || (mant & 1u))) ++mant; /* mant may reach 2^53: still exact */
+  return sign * ldexp((double)mant, top - 52 - 1074);
+}
+
+int orc_exact_sum(const double* x, uint64_t n, double* sum) {
+  if (sum == NULL || (n > 0 && x == NULL)) return -1;
+  exact_sum* s = (exact_sum*)calloc(1, sizeof(exact_sum));
+  if (s == NULL) return -1;
+  for (uint64_t k = 0; k < n; ++k) xs_add(s, x[k]);
+  *sum = xs_round(s);
+  free(s);
+  return 0;
 }
 
 typedef struct {
   int dist, dtype;
   const orc_tables *ex, *nt;
-  uint64_t seed, first, last, blk0, t_lo, t_hi;
+  uint64_t seed, first, lo, hi;
   double scale, shift;
-  double* tile_sums; /* [tiles][5] */
+  exact_sum* acc; /* [10]: S_1..S_5, then |.| sums */
 } mom_job;
 
 static void* mom_worker(void* arg) {
   mom_job* jb = (mom_job*)arg;
-  const uint64_t per = jb->dtype == ORC_F64 ? 2 : 4;
-  static __thread double lanes[MOM_LANES][5];
-  for (uint64_t t = jb->t_lo; t < jb->t_hi; ++t) {
-    for (uint32_t l = 0; l < MOM_LANES; ++l) {
-      double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      for (uint32_t s = 0; s < MOM_TILE_BLOCKS / MOM_LANES; ++s) {
-        const uint64_t b = jb->blk0 + t * MOM_TILE_BLOCKS + l + (uint64_t)MOM_LANES * s;
-        for (uint64_t o = 0; o < per; ++o) {
-          const uint64_t g = b * per + o;
-          if (g < jb->first || g > jb->last) continue;
-          trace_rec tr;
-          double x;
-          if (jb->dtype == ORC_F64)
-            x = sample64(jb->dist, jb->ex, jb->nt, jb->seed, g, jb->scale, jb->shift, &tr);
-          else
-            x = (double)sample32(jb->dist, jb->ex, jb->nt, jb->seed, g, jb->scale, jb->shift, &tr);
-          const double q2 = x * x, q3 = q2 * x, q4 = q2 * q2, q5 = q4 * x;
-          a[0] = a[0] + x;
-          a[1] = a[1] + q2;
-          a[2] = a[2] + q3;
-          a[3] = a[3] + q4;
-          a[4] = a[4] + q5;
-        }
-      }
-      for (int p = 0; p < 5; ++p) lanes[l][p] = a[p];
+  for (uint64_t k = jb->lo; k < jb->hi; ++k) {
+    trace_rec tr;
+    double x;
+    if (jb->dtype == ORC_F64)
+      x = sample64(jb->dist, jb->ex, jb->nt, jb->seed, jb->first + k, jb->scale, jb->shift, &tr);
+    else
+      x = (double)sample32(jb->dist, jb->ex, jb->nt, jb->seed, jb->first + k, jb->scale, jb->shift, &tr);
+    const double q2 = x * x, q3 = q2 * x, q4 = q2 * q2, q5 = q4 * x;
+    const double q[5] = {x, q2, q3, q4, q5};
+    for (int p = 0; p < 5; ++p) {
+      xs_add(&jb->acc[p], q[p]);
+      xs_add(&jb->acc[5 + p], fabs(q[p]));
     }
-    halving_sum(lanes, MOM_LANES);
-    for (int p = 0; p < 5; ++p) jb->tile_sums[t * 5 + p] = lanes[0][p];
   }
   return NULL;
 }
 
 int orc_moments(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, uint64_t seed, uint64_t first,
-                uint64_t n, double scale, double shift, double sums[5], int threads) {
+                uint64_t n, double scale, double shift, double sums[5], double abs_sums[5], int threads) {
   double dummy;
   if (check_args(dist, dtype, ex, nt, first, n, &dummy) || sums == NULL) return -1;
-  for (int p = 0; p < 5; ++p) sums[p] = 0.0;
-  if (n == 0) return 0;
-  const uint64_t per = dtype == ORC_F64 ? 2 : 4;
-  const uint64_t last = first + (n - 1);
-  const uint64_t blk0 = first / per;
-  const uint64_t blocks = last / per - blk0 + 1;
-  const uint64_t tiles = (blocks + MOM_TILE_BLOCKS - 1) / MOM_TILE_BLOCKS;
-  double* tile_sums = (double*)malloc(tiles * 5 * sizeof(double));
-  if (tile_sums == NULL) return -1;
   if (threads < 1) threads = 1;
   if (threads > 256) threads = 256;
-  if ((uint64_t)threads > tiles) threads = (int)tiles;
+  if ((uint64_t)threads > n) threads = n > 0 ? (int)n : 1;
+  exact_sum* acc = (exact_sum*)calloc((size_t)threads * 10, sizeof(exact_sum));
+  if (acc == NULL) return -1;
   mom_job jobs[256];
   pthread_t tid[256];
   for (int k = 0; k < threads; ++k) {
@@ -795,13 +881,11 @@ int orc_moments(int dist, int dtype, const orc_tables* ex, const orc_tables* nt,
     jb->nt = nt;
     jb->seed = seed;
     jb->first = first;
-    jb->last = last;
-    jb->blk0 = blk0;
-    jb->t_lo = tiles * (uint64_t)k / (uint64_t)threads;
-    jb->t_hi = tiles * (uint64_t)(k + 1) / (uint64_t)threads;
+    jb->lo = n * (uint64_t)k / (uint64_t)threads;
+    jb->hi = n * (uint64_t)(k + 1) / (uint64_t)threads;
     jb->scale = scale;
     jb->shift = shift;
-    jb->tile_sums = tile_sums;
+    jb->acc = acc + (size_t)k * 10;
   }
   if (threads == 1) {
     mom_worker(&jobs[0]);
@@ -809,14 +893,13 @@ int orc_moments(int dist, int dtype, const orc_tables* ex, const orc_tables* nt,
     for (int k = 0; k < threads; ++k) pthread_create(&tid[k], NULL, mom_worker, &jobs[k]);
     for (int k = 0; k < threads; ++k) pthread_join(tid[k], NULL);
   }
-  double group[MOM_LANES][5];
-  for (uint64_t g0 = 0; g0 < tiles; g0 += MOM_LANES) {
-    for (uint32_t i = 0; i < MOM_LANES; ++i)
-      for (int p = 0; p < 5; ++p) group[i][p] = (g0 + i < tiles) ? tile_sums[(g0 + i) * 5 + p] : 0.0;
-    halving_sum(group, MOM_LANES);
-    for (int p = 0; p < 5; ++p) sums[p] = sums[p] + group[0][p];
+  for (int k = 1; k < threads; ++k)
+    for (int p = 0; p < 10; ++p) xs_merge(&acc[p], &acc[(size_t)k * 10 + p]);
+  for (int p = 0; p < 5; ++p) {
+    sums[p] = xs_round(&acc[p]);
+    if (abs_sums) abs_sums[p] = xs_round(&acc[5 + p]);
   }
-  free(tile_sums);
+  free(acc);
   return 0;
 }
 

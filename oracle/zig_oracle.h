@@ -94,12 +94,17 @@ int orc_fill_trace(int dist, int dtype, const orc_tables* ex, const orc_tables* 
                    int32_t* region, uint32_t* words, uint32_t* tests);
 
 /* Raw moment sums S_p = sum of x^p, p = 1..5, over the outputs a fill of
- * the same arguments writes, added in the fixed order described in
- * zig_oracle.c (lane sums over 2048-block tiles, halving trees over lanes
- * and over groups of 256 tiles, then the groups in order).  Uses `threads`
- * POSIX threads over tiles; the result does not depend on it. */
+ * the same arguments writes (powers by double multiplication: x*x, then
+ * *x, squared, *x), each the exact sum rounded once to double, so no order
+ * of addition enters; abs_sums (may be NULL) receives sum |x^p| the same
+ * way.  Uses `threads` POSIX threads over contiguous index ranges; the
+ * result does not depend on it. */
 int orc_moments(int dist, int dtype, const orc_tables* ex, const orc_tables* nt, uint64_t seed, uint64_t first,
-                uint64_t n, double scale, double shift, double sums[5], int threads);
+                uint64_t n, double scale, double shift, double sums[5], double abs_sums[5], int threads);
+
+/* The exact sum of x[0..n-1] rounded once to double (to nearest, ties to
+ * even; +0 for an exact zero, NaN if a term is not finite). */
+int orc_exact_sum(const double* x, uint64_t n, double* sum);
 
 /* One rejection attempt in overhang/cap box j (1..L) with injected
  * 53-bit integers k1, k2.  Returns 1 and sets *x on acceptance. */

@@ -1,10 +1,14 @@
-"""Pins of the oracle's raw-moment sums (the fused generate-and-reduce
-form): the fixed summation order stays within the proven error bound of
-the correctly rounded sum (math.fsum) of the same powers, the result does
-not depend on the thread count, empty and one-output ranges, FP32 outputs
-widened before the powers, and the sample moments against the closed forms
-E[X^p] = p!/lambda^p (exponential) and the normal raw moments (Appendix B
-tabulates X1..X5 of 10^12 draws against 1, 2, 6, 24, 120 and 0, 1, 0, 3, 0)."""
+"""Pins of the oracle's raw-moment sums (Appendix B's statistic, section
+3's generate-and-aggregate form).
+
+The oracle adds every term exactly and rounds once, so its sums must equal
+Python's math.fsum (Shewchuk's correctly rounded summation, an independent
+algorithm) bit for bit: first on hand-made and random arrays that stress
+rounding (ties, cancellation, subnormals, wide exponent ranges), then on
+the powers of the oracle's own fill outputs.  The sample moments are
+checked against the closed forms E[X^p] = p!/lambda^p (exponential) and
+the normal raw moments (Appendix B tabulates X1..X5 of 10^12 draws against
+1, 2, 6, 24, 120 and 0, 1, 0, 3, 0)."""
 import math
 
 import numpy as np
@@ -22,31 +26,61 @@ def powers(x):
     return [x, q2, q3, q4, q5]
 
 
-def order_depth(n, per):
-    """Longest chain of additions in the fixed order: a lane adds at most
-    8 * per outputs, then 8 halving levels over lanes, 8 over tiles, then
-    the groups one after the other."""
-    tiles = -(-n // (2048 * per)) + 1
-    groups = -(-tiles // 256)
-    return 8 * per + 8 + 8 + groups + 1
+def bits(v):
+    return np.float64(v).view(np.uint64)
+
+
+@pytest.mark.parametrize("xs,want", [
+    ([], 0.0),
+    ([2.5], 2.5),
+    ([1.0, 2.0 ** -53], 1.0),                          # tie, to even (down)
+    ([1.0 + 2.0 ** -52, 2.0 ** -53], 1.0 + 2.0 ** -51),  # tie, to even (up)
+    ([1.0, 2.0 ** -53, 2.0 ** -105], 1.0 + 2.0 ** -52),  # just above the tie
+    ([1.0, -(2.0 ** -53)], 1.0 - 2.0 ** -53),          # exact below 1
+    ([1.0, -(2.0 ** -54)], 1.0),                        # tie below 1, to even
+    ([1.0, -(2.0 ** -54), -(2.0 ** -200)], 1.0 - 2.0 ** -53),
+    ([1e300, 1.0, -1e300], 1.0),                        # cancellation
+    ([5e-324, 5e-324, -5e-324], 5e-324),               # subnormals
+    ([2.0 ** -1022, -(2.0 ** -1074)], 2.0 ** -1022 - 2.0 ** -1074),
+    ([1.0, -1.0], 0.0),
+])
+def test_exact_sum_hand_cases(O, xs, want):
+    got = O.exact_sum(np.array(xs, dtype=np.float64))
+    assert bits(got) == bits(want), (xs, got, want)
+
+
+def test_exact_sum_zero_is_positive(O):
+    assert bits(O.exact_sum(np.array([-0.0]))) == bits(0.0)
+    assert bits(O.exact_sum(np.array([3.0, -3.0]))) == bits(0.0)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_exact_sum_equals_fsum(O, seed):
+    rng = np.random.default_rng(seed)
+    for _ in range(50):
+        n = int(rng.integers(1, 3000))
+        span = int(rng.choice([4, 60, 400, 1500]))
+        e = rng.integers(-span, span, n)
+        x = rng.standard_normal(n) * np.exp2(np.clip(e, -1070, 1000).astype(np.float64))
+        if rng.random() < 0.3:  # near-cancelling tails
+            x = np.concatenate([x, -x[: n // 2] * (1 + 2.0 ** -52)])
+        rng.shuffle(x)
+        got = O.exact_sum(x)
+        want = math.fsum(x)
+        assert bits(got) == bits(want) or (got == 0.0 and want == 0.0), (got, want)
 
 
 @pytest.mark.parametrize("dist,dtype,first,n,p0,p1", [
     (EXP, F64, 0, 1_000_003, 1.0, 0.0), (NORMAL, F64, 7, 600_001, -1.0, 3.0),
     (EXP, F32, 3, 900_000, 2.5, 0.0), (NORMAL, F32, 2 ** 40 + 1, 555_555, 0.5, 0.25),
     (EXP, F64, 1, 4096 * 300 + 17, 0.3, 0.0)])
-def test_fixed_order_within_bound_of_exact_sum(O, dist, dtype, first, n, p0, p1):
+def test_moments_equal_fsum_of_fill_powers(O, dist, dtype, first, n, p0, p1):
     scale, shift = (1.0 / p0, 0.0) if dist == EXP else (p1, p0)
-    got = O.moments(dist, dtype, 42, first, n, scale, shift, threads=8)
+    got, gabs = O.moments(dist, dtype, 42, first, n, scale, shift, threads=8, with_abs=True)
     x = O.fill(dist, dtype, 42, first, n, scale, shift, threads=8)
-    per = 2 if dtype == F64 else 4
-    h = order_depth(n, per)
-    u = 2.0 ** -53
-    gamma = h * u / (1 - h * u)
     for p, q in enumerate(powers(x)):
-        exact = math.fsum(q)
-        bound = gamma * math.fsum(np.abs(q)) + 1e-300
-        assert abs(got[p] - exact) <= bound, (p, got[p], exact, bound)
+        assert bits(got[p]) == bits(math.fsum(q)), (p, got[p], math.fsum(q))
+        assert bits(gabs[p]) == bits(math.fsum(np.abs(q))), p
 
 
 def test_thread_count_does_not_matter(O):
@@ -74,6 +108,7 @@ def test_sample_moments_match_closed_forms(O, dist, lam_or_mu, sigma):
         got = O.moments(EXP, F64, 77, 0, n, 1.0 / lam, 0.0, threads=8) / n
     else:
         mu, s = lam_or_mu, sigma
+
         # raw moments of N(mu, s^2): sum over even k of C(p,k) mu^(p-k) s^k (k-1)!!
         def raw(p):
             return sum(math.comb(p, k) * mu ** (p - k) * s ** k * math.prod(range(k - 1, 0, -2))
