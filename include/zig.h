@@ -15,9 +15,18 @@
  *    framework allocation); capacity >= n * element size, aligned to the
  *    element size.  The library never frees or retains them.
  *  - `stream` is a hipStream_t passed as an opaque pointer; NULL is the
- *    default stream of the current device.  Fills are asynchronous: they
- *    return after enqueueing, launch failures return ZIG_EHIP, and a
- *    device fault surfaces at the caller's next synchronisation.
+ *    default stream of the current device (hipStreamPerThread is accepted
+ *    too).  Fills are asynchronous: they return after enqueueing, launch
+ *    failures return ZIG_EHIP, and a device fault surfaces at the caller's
+ *    next synchronisation.
+ *  - Scratch: a fill of more than 16 tiles per compute unit takes its
+ *    tiles from an atomic counter pair; the library owns a ring of 64 such
+ *    pairs per device (allocated on first use, kept until the process
+ *    ends) and gives each launch its own, behind an event, so concurrent
+ *    fills on any streams and threads never share one.  Smaller fills, and
+ *    every fill enqueued on a stream that is being captured into a graph,
+ *    use a fixed tile-to-workgroup schedule with no scratch, so a captured
+ *    graph may be replayed on several streams at once.
  *  - Determinism: the output at global index k is a pure function of
  *    (distribution, dtype, seed, k, parameters, i_max).  It does not depend
  *    on the stream, launch shape, batch composition or call splitting:
@@ -215,22 +224,30 @@ int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
 
 /* Fused generate-and-reduce: the raw moment sums S_p = sum over k of x_k^p,
  * p = 1..5, of the n outputs x_k that zig_fill with the same arguments
- * would write (as written: doubles, or floats widened to double; powers
- * formed as x*x, x^2*x, x^2*x^2, x^4*x), written to sums[0..4] in device
- * memory (caller-owned, 8-byte aligned); no output is written to HBM.  This
- * is the generate-and-aggregate form of the paper's benchmark (section 3)
- * and of Appendix B's raw-moment test.  The additions follow one fixed
- * order, so the result is the same bits on every run and device: tiles of
- * 2048 Philox blocks from the first block (first_index / 2 for FP64, / 4
- * for FP32); in a tile, lane l = 0..255 adds, from +0, the outputs of
- * blocks l, l + 256, ..., l + 1792 in order; the 256 lane sums are reduced
- * by halving (v[l] += v[l + s] for s = 128, 64, ..., 1); groups of 256
- * tiles likewise (the last one padded with +0); the total is +0 plus the
- * group sums in order.  launch may be NULL; only launch->i_max (up to 256)
- * and ZIG_LAUNCH_NORMAL_ACCEL are honoured (wg and spl must be 0 or 256
- * and 8).  Asynchronous on `stream`; uses
- * 2.6 MB of device scratch per stream, kept until the process ends.
- * Errors: as zig_fill (sums in place of out). */
+ * would write (as written: doubles, or floats widened to double), written
+ * to sums[0..4] in device memory (caller-owned, 8-byte aligned); no output
+ * is written to HBM.  This is the generate-and-aggregate form of the
+ * paper's benchmark (section 3) and the statistic of Appendix B's
+ * raw-moment table.
+ * Each term is formed by double products (x*x, then its square; the odd
+ * powers multiply by x fused with their addition) and added in an order
+ * fixed by the launch: workgroup w of G takes the tiles w, w + G, ... of
+ * 256 * spl Philox blocks from first_index / 2 (FP64) or / 4 (FP32); each
+ * lane adds its own terms, at most 2 * spl * O per tile (O = 2 outputs per
+ * block for FP64, 4 for FP32); lane sums are added over each wave by a
+ * shuffle tree, over the 4 waves in order, and the G partial sums by 256
+ * lanes in sequence and a halving tree.  G is the number of resident
+ * workgroups of the kernel (at least min(tiles, compute units), at most
+ * 4096), so a device gives the same bits on every run.  The result
+ * therefore differs from the exact sum of the same terms by at most
+ * gamma_h * sum |x_k^p| + 2^-53 sum |x_k^p|, gamma_h = h u / (1 - h u),
+ * u = 2^-53, h = 2 spl O ceil(tiles / G) + ceil(G / 256) + 18.
+ * launch may be NULL; launch->i_max (up to 256), launch->spl (16, 32 or
+ * 64; default 32, with wg 0 or 256) and ZIG_LAUNCH_NORMAL_ACCEL are
+ * honoured.  Asynchronous on `stream`; each launch takes one of 4
+ * per-device scratch slots of 160 KB (partial sums), behind an event.  A
+ * stream being captured is refused (ZIG_EINVAL): a graph would fix the
+ * slot.  Errors: as zig_fill (sums in place of out). */
 int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
                 double* sums, void* stream, const zig_launch* launch);
 

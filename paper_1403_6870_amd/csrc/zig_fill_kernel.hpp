@@ -181,11 +181,6 @@ __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a,
 // One tile (tile index t of this launch).  Ends with the staging tile
 // written out; callers separate consecutive tiles with a barrier.
 //
-// With MOM set, phase C instead reduces the tile to its raw moment sums
-// (S1..S5 into msum[0..4]) in the fixed order of the moments definition:
-// lane l adds the outputs of its blocks l + WG * s in order of s, then the
-// lane sums are reduced by halving.
-//
 // With TRAD set (FP64 only) the sampler is the traditional ziggurat: the
 // fast word quick-accepts when its magnitude bits lie below the layer's
 // threshold, and phase B runs the traditional slow path from that word.
@@ -193,10 +188,9 @@ __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a,
 // WIDE marks tables of more than 256 layers: a 32-bit word then gives
 // s = b > 8 low bits to the index, so its magnitude starts at bit s (the
 // normal's sign sits at bit s); otherwise s = 8.
-template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool MOM = false, bool ACCEL = false,
-          bool TRAD = false, bool WIDE = false>
-__device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t,
-                                          double* msum = nullptr) {
+template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
+          bool WIDE = false>
+__device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t) {
   using Sh = FillShape<DT, WG, S>;
   using OutT = typename Sh::OutT;
   using VecT = typename Sh::VecT;
@@ -204,7 +198,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   constexpr int NWAVE = Sh::NWAVE;
   constexpr int NWORD = Sh::NWORD;
   constexpr int TILE = Sh::TILE;
-  static_assert(!TRAD || (DT == kF64 && !TRACE && !MOM && !ACCEL), "traditional sampler: plain FP64 fills");
+  static_assert(!TRAD || (DT == kF64 && !TRACE && !ACCEL), "traditional sampler: plain FP64 fills");
 
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
@@ -400,58 +394,6 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   }
   __syncthreads();
 
-  if constexpr (MOM) {
-    static_assert(WG == 256 && S == 8, "the moments order is defined on 256 lanes x 8 blocks");
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;
-      const VecT vv = stage[s * WG + tid];
-      const OutT* pv = reinterpret_cast<const OutT*>(&vv);
-#pragma unroll
-      for (int o = 0; o < O; ++o) {
-        const uint64_t g = m * O + o;
-        if (interior || (m <= a.blk_last && g >= a.first && g <= a.last)) {
-          const double x = (double)pv[o];
-          const double q2 = x * x, q3 = q2 * x, q4 = q2 * q2, q5 = q4 * x;
-          acc[0] = acc[0] + x;
-          acc[1] = acc[1] + q2;
-          acc[2] = acc[2] + q3;
-          acc[3] = acc[3] + q4;
-          acc[4] = acc[4] + q5;
-        }
-      }
-    }
-    __syncthreads();  // every lane has read its blocks; the staging tile is reused
-    double* red = static_cast<double*>(sh.stage);  // [5][WG]
-#pragma unroll
-    for (int p = 0; p < 5; ++p) red[p * WG + tid] = acc[p];
-    __syncthreads();
-    if (tid < 128) {  // level 128 across waves
-#pragma unroll
-      for (int p = 0; p < 5; ++p) red[p * WG + tid] = red[p * WG + tid] + red[p * WG + tid + 128];
-    }
-    __syncthreads();
-    if (tid < 64) {  // level 64, then 32 .. 1 inside wave 0 (the same pairs)
-      double v[5];
-#pragma unroll
-      for (int p = 0; p < 5; ++p) v[p] = red[p * WG + tid] + red[p * WG + tid + 64];
-#pragma unroll
-      for (int h = 32; h >= 1; h >>= 1) {
-#pragma unroll
-        for (int p = 0; p < 5; ++p) {
-          const double up = __shfl_down(v[p], h);
-          if ((int)tid < h) v[p] = v[p] + up;
-        }
-      }
-      if (tid == 0) {
-#pragma unroll
-        for (int p = 0; p < 5; ++p) msum[p] = v[p];
-      }
-    }
-    return;
-  }
-
   // C: staging tile to HBM.  An interior tile with 16-byte aligned blocks
   // (the common case) stores from one uniform base pointer at lane offsets.
   if (interior && a.aligned16) {
@@ -511,6 +453,14 @@ fill_kernel(FillArgs a) {
   tl.stage = sh.stage;
   tl.slowmap = sh.slowmap;
   tl.prefix = sh.prefix;
+  if (a.counters == nullptr) {  // static schedule
+    __syncthreads();  // the tables in LDS are complete
+    for (uint64_t t = blockIdx.x; t < a.tiles; t += gridDim.x) {
+      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE>(a, c, tl, (uint32_t)t);
+      __syncthreads();
+    }
+    return;
+  }
   for (;;) {
     if (threadIdx.x == 0) sh.tile = atomicAdd(&a.counters[0], 1u);
     __syncthreads();
@@ -518,7 +468,7 @@ fill_kernel(FillArgs a) {
     if (t0 >= a.tiles) break;
     const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
     for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, WG, S, TRACE, false, ACCEL, TRAD, WIDE>(a, c, tl, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE>(a, c, tl, (uint32_t)t);
       __syncthreads();
     }
   }
@@ -566,6 +516,11 @@ int launch_one(const FillArgs& args, hipStream_t st) {
   int e = resident_groups(kernel, WG, 0, &groups);
   if (e != 0) return e;
   FillArgs a = args;
+  if (a.counters == nullptr) {
+    const uint32_t grid = a.tiles < (uint64_t)groups ? a.tiles : (uint32_t)groups;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(WG), 0, st, a);
+    return (int)hipGetLastError();
+  }
   // tiles per counter step: as asked, but small enough that every resident
   // workgroup gets a couple of steps
   uint64_t chunk = a.tiles / (2ull * (uint64_t)groups);

@@ -93,7 +93,8 @@ struct FillArgs {
   double scale, shift;
   const DevTable* tab;   // tables of the distribution
   const DevTable* etab;  // exponential tables (normal tail)
-  uint32_t* counters;    // [0] next tile, [1] workgroups done; zero between launches
+  uint32_t* counters;    // [0] next tile step, [1] workgroups done, zero between launches;
+                         // null: workgroup w takes tiles w, w + grid, ...
   uint32_t tiles;        // tiles of WG * S blocks in this launch
   uint32_t chunk;        // tiles taken per step of the counter
   uint32_t aligned16;    // 16-byte block stores are aligned
@@ -111,6 +112,10 @@ struct FillArgs {
   const DevTrad* tetab;
 };
 
+// Fills of at most this many tiles per compute unit use the static tile
+// schedule (a.counters null); larger ones take tiles from a counter pair.
+constexpr uint32_t kStaticTilesPerCU = 16;
+
 // Launch of one (dist, dtype, wg, spl) variant over a.tiles tiles, with as
 // many persistent workgroups as fit on the device; defined in zig_fill.hip.
 // Returns 0 or a hipError_t value.
@@ -126,14 +131,14 @@ int launch_fill_wide(uint32_t dist, uint32_t dtype, uint32_t wg, uint32_t spl, b
 // and a.tetab set.
 int launch_trad(uint32_t dist, uint32_t wg, uint32_t spl, const FillArgs& a, void* stream);
 
-// Raw moments (zig_moments.hip): one segment of at most kMomSegTiles tiles
-// of 2048 blocks (a.tiles, a.blk0 set by the caller); tile_sums holds
-// 5 * kMomSegTiles doubles, group_sums 5 * kMomSegTiles / 256.  Returns 0 or
-// a hipError_t value.
-constexpr uint32_t kMomTileBlocks = 2048;
-constexpr uint32_t kMomSegTiles = 1u << 16;
-int launch_moments_segment(uint32_t dist, uint32_t dtype, const FillArgs& a, double* tile_sums, double* group_sums,
-                           double* sums, bool accumulate, void* stream);
+// Raw moments (zig_moments.hip): a.tiles is unused; `tiles` tiles of
+// 256 * spl Philox blocks from a.blk0.  At most max_groups workgroups run,
+// each writing its 5 partial sums to partial[5 * w ..]; a second kernel
+// writes their total to sums.  Returns 0 or a hipError_t value.
+constexpr uint32_t kMomMaxGroups = 4096;
+bool moments_spl_supported(uint32_t spl);
+int launch_moments(uint32_t dist, uint32_t dtype, uint32_t spl, const FillArgs& a, uint64_t tiles, double* partial,
+                   uint32_t max_groups, double* sums, void* stream);
 int launch_moments_zero(double* sums, void* stream);
 
 // One request of a batch as the batch kernel reads it (device memory).

@@ -1,18 +1,31 @@
 // Fused generate-and-reduce: the raw moment sums S_p = sum of x^p, p = 1..5,
-// of the outputs a fill would write, with no output written to HBM.
+// of the outputs a fill would write, with nothing written to HBM (the
+// generate-and-aggregate form of the paper's benchmark, section 3, and the
+// statistic of Appendix B's raw-moment table).
 //
-// The summation order is part of the definition, so that the result is the
-// same bits whatever the launch shape or scheduling:
-//   - tiles of 2048 Philox blocks from the fill's first block; in a tile,
-//     lane l (0..255) adds the outputs of blocks l, l + 256, ..., l + 1792
-//     in order (the fill's own tile code, with the tile reduced instead of
-//     stored), and the lane sums are reduced by halving;
-//   - groups of 256 tiles are reduced the same way (the last group padded
-//     with zeros);
-//   - the total is +0 plus the group sums in order.
-// A fill is processed in segments of 2^16 tiles (256 groups): the tile
-// kernel writes per-tile sums, the group kernel per-group sums, and the
-// total kernel continues the running total in `sums`.
+// Each lane keeps five running sums for the whole launch.  Workgroup w of
+// G takes tiles w, w + G, w + 2G, ... (a fixed assignment, so the result is
+// the same bits on every run with the same G, which depends only on the
+// device).  Per tile:
+//   A. every lane computes its S Philox blocks; an output on the fast path
+//      (layer i < L) is added to the lane's sums at once; slow outputs are
+//      recorded in an LDS bitmap by wave ballots (no staging tile);
+//   B. wave 0 numbers the slow outputs by prefix sums over the bitmap, and
+//      every lane takes a share of them, runs the slow path (region,
+//      overhang box or tail) and adds the result to its own sums.
+// The bitmap and its prefix sums are double-buffered by tile parity, so
+// one barrier after phase A and one after the prefix suffice.  At the end
+// the lane sums are reduced over each wave (shuffle tree), over the waves
+// in order, and written per workgroup; a second kernel adds the G partial
+// sums (256 lanes in sequence, then a halving tree).
+//
+// Every term is x^p formed from the output as written (FP32 widened to
+// double) by products x*x, (x*x)*x, (x*x)^2, (x*x)^2*x, the multiplications
+// by x of the odd powers fused with their addition.  A lane adds at most
+// 2 S O terms per tile it takes (O outputs per block; S O of its own
+// blocks and at most as many slow outputs), so the rounding error of S_p
+// is at most gamma_h sum |x^p| + u sum |x^p| with
+// h = 2 S O ceil(tiles / G) + 6 + WG / 64 + ceil(G / 256) + 8.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -25,44 +38,264 @@ namespace zig {
 namespace {
 
 constexpr int kMomWG = 256;
-constexpr int kMomS = 8;
 
-template <uint32_t DIST, uint32_t DT, bool ACCEL>
-__global__ void __launch_bounds__(kMomWG) moments_kernel(FillArgs a, double* tile_sums) {
-  // the slow-path tables stay in device memory, as in the fill's 256 x 8
-  // kernel: one more workgroup per CU
-  __shared__ FillLds<DT, kMomWG, kMomS, kLdsLayers, !lean_shape(kMomWG, kMomS)> sh;
-  const FillCtx c = load_tables<DIST, DT, kMomWG, kMomS, kLdsLayers, !lean_shape(kMomWG, kMomS)>(a, sh);
-  TileLds tl;
-  tl.stage = sh.stage;
-  tl.slowmap = sh.slowmap;
-  tl.prefix = sh.prefix;
-  for (;;) {
-    if (threadIdx.x == 0) sh.tile = atomicAdd(&a.counters[0], 1u);
+// Tile of 256 lanes x S Philox blocks (no staging tile, so larger tiles
+// than the fill's fit).
+template <uint32_t DT, int S>
+struct MomShape {
+  using OutT = typename OutType<DT>::T;
+  static constexpr int O = OutType<DT>::per_block;
+  static constexpr int TILE = kMomWG * S;
+  static constexpr int NWAVE = kMomWG / 64;
+  static constexpr int NWORD = S * O * NWAVE;
+  static_assert(NWORD <= 1024, "tile shape");
+};
+
+template <uint32_t DT, int S>
+struct MomLds {
+  using Sh = MomShape<DT, S>;
+  typename Sh::OutT xs[kLdsLayers];  // fast-path table, 0 for i >= L
+  double X[kLdsLayers + 1];
+  double f[kLdsLayers + 1];
+  uint64_t T[kLdsLayers];
+  uint32_t A[kLdsLayers];
+  uint64_t slowmap[2][Sh::NWORD];
+  uint32_t prefix[2][Sh::NWORD + 1];
+  double red[5][Sh::NWAVE];
+};
+
+__device__ __forceinline__ void add_powers(double (&acc)[5], double x) {
+  const double q2 = x * x;
+  const double q4 = q2 * q2;
+  acc[0] = acc[0] + x;
+  acc[1] = acc[1] + q2;
+  acc[2] = __builtin_fma(q2, x, acc[2]);
+  acc[3] = acc[3] + q4;
+  acc[4] = __builtin_fma(q4, x, acc[4]);
+}
+
+// Five waves per SIMD, and phase A unrolled by two blocks rather than fully,
+// which keeps the kernel near 90 registers with nothing spilled: measured
+// at 2^32 FP64 outputs on 256 x 32 tiles against 256 x 8 fully unrolled
+// (three waves), 572 -> 741 Gsamples/s for the exponential and 462 -> 616
+// for the normal.  Six waves measured 3 % faster but spill to scratch.
+template <uint32_t DIST, uint32_t DT, int S, bool ACCEL>
+__global__ void __launch_bounds__(kMomWG) __attribute__((amdgpu_waves_per_eu(5)))
+moments_kernel(FillArgs a, uint64_t tiles, double* partial) {
+  using Sh = MomShape<DT, S>;
+  using OutT = typename Sh::OutT;
+  constexpr int WG = kMomWG;
+  constexpr int O = Sh::O;
+  constexpr int NWAVE = Sh::NWAVE;
+  constexpr int NWORD = Sh::NWORD;
+  constexpr int TILE = Sh::TILE;
+  __shared__ MomLds<DT, S> sh;
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t wave = tid >> 6;
+  const DevTable* tb = a.tab;
+  const uint32_t L = tb->L;
+  for (uint32_t i = tid; i < kLdsLayers; i += WG) {
+    if constexpr (DT == kF64)
+      sh.xs[i] = i < L ? tb->XS[i] : 0.0;
+    else
+      sh.xs[i] = i < L ? tb->XS32[i] : 0.0f;
+    sh.T[i] = tb->T[i];
+    sh.A[i] = tb->A[i];
+  }
+  for (uint32_t i = tid; i <= kLdsLayers; i += WG) {
+    sh.X[i] = tb->X[i];
+    sh.f[i] = tb->f[i];
+  }
+  dev::TabView own = dev::global_view(tb);
+  own.X = sh.X;
+  own.f = sh.f;
+  own.T = sh.T;
+  own.A = sh.A;
+  const dev::TabView ex = dev::global_view(a.etab);
+  const uint32_t imask = own.imask;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const double scale = a.scale;
+  const float fscale = (float)a.scale;
+  double shiftv = a.shift;
+  float fshift = (float)a.shift;
+  if constexpr (DIST == kDistNormal) asm volatile("" : "+v"(shiftv), "+v"(fshift));
+  __syncthreads();
+
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  uint32_t parity = 0;
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x, parity ^= 1u) {
+    const uint64_t tile0 = a.blk0 + t * TILE;
+    const bool interior = a.has_full && tile0 >= a.full_lo && tile0 + (TILE - 1) <= a.full_hi;
+    uint64_t* const slowmap = sh.slowmap[parity];
+    uint32_t* const prefix = sh.prefix[parity];
+    // this wave's first bitmap word, as an LDS address
+    const uint32_t lds_word = dev::lds_address(slowmap + wave);
+
+    // A: fast outputs into the sums, slow ones into the bitmap
+    auto phase_a = [&](auto interior_tag) {
+      constexpr bool IN = decltype(interior_tag)::value;
+#pragma unroll 2
+      for (int s = 0; s < S; ++s) {
+        const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;
+        uint32_t c0 = (uint32_t)m, c1 = (uint32_t)(m >> 32), c2 = 0u, c3 = (DT == kF64) ? 0u : 1u;
+        dev::philox10(c0, c1, c2, c3, k0, k1);
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+          const uint64_t g = m * O + o;
+          bool live = true;
+          if constexpr (!IN) live = (m <= a.blk_last) && (g >= a.first) && (g <= a.last);
+          uint32_t i;
+          OutT x;
+          if constexpr (DT == kF64) {
+            const uint32_t lo = (o == 0) ? c0 : c2, hi = (o == 0) ? c1 : c3;
+            i = lo & imask;
+            const double k = __builtin_fma((double)hi, 0x1p21, (double)(lo >> 11));
+            x = k * sh.xs[i];
+            if constexpr (DIST == kDistNormal) x = dev::with_sign_of(x, lo << 21);
+          } else {
+            const uint32_t w = (o == 0) ? c0 : (o == 1) ? c1 : (o == 2) ? c2 : c3;
+            i = w & imask;
+            if constexpr (DIST == kDistExp) {
+              x = (float)(w >> 8) * sh.xs[i];
+            } else {
+              x = (float)(w >> 9) * sh.xs[i];
+              x = dev::with_sign_of(x, w << 23);
+            }
+          }
+          const bool miss = i >= L;
+          const bool slow = live && miss;
+          double v;
+          // the exponential's slow placeholder is scale * 0 = +0, which
+          // adds nothing; the normal's is mu and is masked out
+          if constexpr (DIST == kDistExp) {
+            if constexpr (DT == kF64)
+              v = scale * x;
+            else
+              v = (double)(fscale * x);
+            if constexpr (!IN) v = live ? v : 0.0;
+          } else {
+            if constexpr (DT == kF64)
+              v = __builtin_fma(scale, x, shiftv);
+            else
+              v = (double)__builtin_fmaf(fscale, x, fshift);
+            v = (live && !miss) ? v : 0.0;
+          }
+          add_powers(acc, v);
+          const uint64_t mask = __builtin_amdgcn_ballot_w64(slow);
+          dev::store_from_lane0(lds_word + (s * O + o) * NWAVE * 8, mask, 0);
+        }
+      }
+    };
+    if (interior)
+      phase_a(std::true_type());
+    else
+      phase_a(std::false_type());
     __syncthreads();
-    const uint64_t t0 = (uint64_t)sh.tile * a.chunk;
-    if (t0 >= a.tiles) break;
-    const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
-    for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, kMomWG, kMomS, false, true, ACCEL>(a, c, tl, (uint32_t)t, tile_sums + 5 * t);
-      __syncthreads();
+
+    // B: number the slow outputs and share them out over every lane
+    if (wave == 0) {
+      constexpr int PER = (NWORD + 63) / 64;
+      uint32_t cnt[PER];
+      uint32_t mine = 0;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int w = lane * PER + k;
+        cnt[k] = (w < NWORD) ? (uint32_t)__popcll(slowmap[w]) : 0u;
+        mine += cnt[k];
+      }
+      uint32_t incl = mine;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t up = __shfl_up(incl, d);
+        if ((int)lane >= d) incl += up;
+      }
+      uint32_t run = incl - mine;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int w = lane * PER + k;
+        if (w < NWORD) prefix[w] = run;
+        run += cnt[k];
+      }
+      if (lane == 63) prefix[NWORD] = incl;
+    }
+    __syncthreads();
+    const uint32_t total = prefix[NWORD];
+    for (uint32_t e = tid; e < total; e += WG) {
+      uint32_t lo = 0, hi = NWORD;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= e)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      uint64_t bits = slowmap[lo];
+      for (uint32_t r = e - prefix[lo]; r > 0; --r) bits &= bits - 1;
+      const uint32_t ln = (uint32_t)__ffsll((unsigned long long)bits) - 1;
+      const uint32_t so = lo / NWAVE, wv = lo % NWAVE;
+      const uint32_t s = so / O, o = so % O;
+      const uint64_t g = (tile0 + s * WG + wv * 64 + ln) * O + o;
+      bool neg = false;
+      if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, k0, k1, 8u);
+      int32_t region;
+      uint32_t words, tests;
+      const double mag = dev::slow_magnitude<DIST, ACCEL>(own, ex, g, k0, k1, region, words, tests);
+      OutT x = (OutT)mag;
+      if (neg) x = -x;
+      double v;
+      if constexpr (DIST == kDistExp) {
+        if constexpr (DT == kF64)
+          v = scale * x;
+        else
+          v = (double)(fscale * x);
+      } else {
+        if constexpr (DT == kF64)
+          v = __builtin_fma(scale, x, a.shift);
+        else
+          v = (double)__builtin_fmaf(fscale, x, fshift);
+      }
+      add_powers(acc, v);
+    }
+    // no barrier: the next tile writes the other bitmap, and the one after
+    // comes behind that tile's two barriers
+  }
+
+  // lane sums -> wave sums (shuffle tree) -> workgroup sums (waves in order)
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      const double up = __shfl_down(acc[p], h);
+      if ((int)lane < h) acc[p] = acc[p] + up;
     }
   }
-  if (threadIdx.x == 0) {
-    if (atomicAdd(&a.counters[1], 1u) == gridDim.x - 1) {
-      atomicExch(&a.counters[0], 0u);
-      atomicExch(&a.counters[1], 0u);
-    }
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < 5; ++p) sh.red[p][wave] = acc[p];
+  }
+  __syncthreads();
+  if (tid < 5) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) s = s + sh.red[tid][w];
+    partial[(size_t)blockIdx.x * 5 + tid] = s;
   }
 }
 
-// Group k = blockIdx.x: halving reduction of tile sums 256k .. 256k + 255.
-__global__ void __launch_bounds__(256) group_kernel(const double* tile_sums, uint32_t tiles, double* group_sums) {
+// sums[p] = the G partial sums of p added by 256 lanes in sequence (lane l
+// takes partials l, l + 256, ...) and a halving tree over the lanes.
+__global__ void __launch_bounds__(256) partials_kernel(const double* partial, uint32_t groups, double* sums) {
   __shared__ double red[5][256];
   const uint32_t tid = threadIdx.x;
-  const uint32_t i = blockIdx.x * 256u + tid;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (uint32_t g = tid; g < groups; g += 256) {
 #pragma unroll
-  for (int p = 0; p < 5; ++p) red[p][tid] = i < tiles ? tile_sums[(size_t)i * 5 + p] : 0.0;
+    for (int p = 0; p < 5; ++p) s[p] = s[p] + partial[(size_t)g * 5 + p];
+  }
+#pragma unroll
+  for (int p = 0; p < 5; ++p) red[p][tid] = s[p];
   __syncthreads();
   for (uint32_t h = 128; h >= 1; h >>= 1) {
     if (tid < h) {
@@ -71,16 +304,7 @@ __global__ void __launch_bounds__(256) group_kernel(const double* tile_sums, uin
     }
     __syncthreads();
   }
-  if (tid < 5) group_sums[(size_t)blockIdx.x * 5 + tid] = red[tid][0];
-}
-
-// sums[p] = (running total or +0) + group sums in order; one lane per p.
-__global__ void total_kernel(const double* group_sums, uint32_t groups, double* sums, uint32_t accumulate) {
-  const uint32_t p = threadIdx.x;
-  if (p >= 5) return;
-  double t = accumulate ? sums[p] : 0.0;
-  for (uint32_t k = 0; k < groups; ++k) t = t + group_sums[(size_t)k * 5 + p];
-  sums[p] = t;
+  if (tid < 5) sums[tid] = red[tid][0];
 }
 
 template <class K>
@@ -107,51 +331,52 @@ int resident(K kernel, int* out) {
   return 0;
 }
 
-template <uint32_t DIST, uint32_t DT, bool ACCEL = false>
-int launch_segment(const FillArgs& args, double* tile_sums, hipStream_t st) {
-  auto kernel = moments_kernel<DIST, DT, ACCEL>;
+template <uint32_t DIST, uint32_t DT, int S, bool ACCEL>
+int launch_s(const FillArgs& a, uint64_t tiles, double* partial, uint32_t max_groups, double* sums,
+             hipStream_t st) {
+  auto kernel = moments_kernel<DIST, DT, S, ACCEL>;
   int groups = 0;
   int e = resident(kernel, &groups);
   if (e != 0) return e;
-  FillArgs a = args;
-  uint64_t chunk = a.tiles / (2ull * (uint64_t)groups);
-  if (chunk > a.chunk) chunk = a.chunk;
-  if (chunk < 1) chunk = 1;
-  a.chunk = (uint32_t)chunk;
-  const uint64_t steps = (a.tiles + chunk - 1) / chunk;
-  const uint32_t grid = steps < (uint64_t)groups ? (uint32_t)steps : (uint32_t)groups;
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kMomWG), 0, st, a, tile_sums);
+  uint64_t grid = (uint64_t)groups < tiles ? (uint64_t)groups : tiles;
+  if (grid > max_groups) grid = max_groups;
+  hipLaunchKernelGGL(kernel, dim3((uint32_t)grid), dim3(kMomWG), 0, st, a, tiles, partial);
+  e = (int)hipGetLastError();
+  if (e != 0) return e;
+  hipLaunchKernelGGL(partials_kernel, dim3(1), dim3(256), 0, st, partial, (uint32_t)grid, sums);
   return (int)hipGetLastError();
+}
+
+template <uint32_t DIST, uint32_t DT, bool ACCEL>
+int launch_d(uint32_t spl, const FillArgs& a, uint64_t tiles, double* partial, uint32_t max_groups, double* sums,
+             hipStream_t st) {
+  if (spl == 16) return launch_s<DIST, DT, 16, ACCEL>(a, tiles, partial, max_groups, sums, st);
+  if (spl == 32) return launch_s<DIST, DT, 32, ACCEL>(a, tiles, partial, max_groups, sums, st);
+  if (spl == 64) return launch_s<DIST, DT, 64, ACCEL>(a, tiles, partial, max_groups, sums, st);
+  return (int)hipErrorInvalidConfiguration;
 }
 
 }  // namespace
 
-int launch_moments_segment(uint32_t dist, uint32_t dtype, const FillArgs& a, double* tile_sums, double* group_sums,
-                           double* sums, bool accumulate, void* stream) {
+bool moments_spl_supported(uint32_t spl) { return spl == 16 || spl == 32 || spl == 64; }
+
+int launch_moments(uint32_t dist, uint32_t dtype, uint32_t spl, const FillArgs& a, uint64_t tiles, double* partial,
+                   uint32_t max_groups, double* sums, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int e;
   if (dist == kDistNormal && a.accel)
-    e = dtype == kF64 ? launch_segment<kDistNormal, kF64, true>(a, tile_sums, st)
-                      : launch_segment<kDistNormal, kF32, true>(a, tile_sums, st);
-  else if (dist == kDistExp && dtype == kF64)
-    e = launch_segment<kDistExp, kF64>(a, tile_sums, st);
-  else if (dist == kDistExp && dtype == kF32)
-    e = launch_segment<kDistExp, kF32>(a, tile_sums, st);
-  else if (dist == kDistNormal && dtype == kF64)
-    e = launch_segment<kDistNormal, kF64>(a, tile_sums, st);
-  else
-    e = launch_segment<kDistNormal, kF32>(a, tile_sums, st);
-  if (e != 0) return e;
-  const uint32_t ngroups = (uint32_t)((a.tiles + 255) / 256);
-  hipLaunchKernelGGL(group_kernel, dim3(ngroups), dim3(256), 0, st, tile_sums, (uint32_t)a.tiles, group_sums);
-  e = (int)hipGetLastError();
-  if (e != 0) return e;
-  hipLaunchKernelGGL(total_kernel, dim3(1), dim3(64), 0, st, group_sums, ngroups, sums, accumulate ? 1u : 0u);
-  return (int)hipGetLastError();
+    return dtype == kF64 ? launch_d<kDistNormal, kF64, true>(spl, a, tiles, partial, max_groups, sums, st)
+                         : launch_d<kDistNormal, kF32, true>(spl, a, tiles, partial, max_groups, sums, st);
+  if (dist == kDistExp && dtype == kF64)
+    return launch_d<kDistExp, kF64, false>(spl, a, tiles, partial, max_groups, sums, st);
+  if (dist == kDistExp && dtype == kF32)
+    return launch_d<kDistExp, kF32, false>(spl, a, tiles, partial, max_groups, sums, st);
+  if (dist == kDistNormal && dtype == kF64)
+    return launch_d<kDistNormal, kF64, false>(spl, a, tiles, partial, max_groups, sums, st);
+  return launch_d<kDistNormal, kF32, false>(spl, a, tiles, partial, max_groups, sums, st);
 }
 
 int launch_moments_zero(double* sums, void* stream) {
-  hipLaunchKernelGGL(total_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), nullptr, 0u, sums, 0u);
+  hipLaunchKernelGGL(partials_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), nullptr, 0u, sums);
   return (int)hipGetLastError();
 }
 

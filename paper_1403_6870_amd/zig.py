@@ -429,13 +429,15 @@ def fill_trace(out, dist, seed, first_index=0, p0=1.0, p1=1.0, launch=None, stre
     return out, layer, region, words, tests
 
 
-def moments(dist, dtype, n, seed, first_index=0, p0=1.0, p1=1.0, stream=None, i_max=0):
+def moments(dist, dtype, n, seed, first_index=0, p0=1.0, p1=1.0, stream=None, i_max=0, spl=0, accel=False):
     """Raw moment sums S1..S5 of the n outputs (dtype F64 or F32) as a
     float64 device tensor of 5 elements; nothing else is written."""
     import torch
     sums = torch.empty(5, dtype=torch.float64, device="cuda")
-    zig_moments(dist, dtype, seed, first_index, n, p0, p1, sums.data_ptr(), _stream_ptr(stream),
-                Launch(i_max, 0, 0) if i_max else None)
+    la = None
+    if i_max or spl or accel:
+        la = Launch(i_max, 256 if spl else 0, spl, LAUNCH_NORMAL_ACCEL if accel else 0)
+    zig_moments(dist, dtype, seed, first_index, n, p0, p1, sums.data_ptr(), _stream_ptr(stream), la)
     return sums
 
 

@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an AMD MI355X (gfx950) GPU")
-    config.addinivalue_line("markers", "slow: statistical test over 10^8 draws (CPU, tens of seconds)")
+    config.addinivalue_line("markers", "slow: long test: 10^8-draw statistics, or every output of a 2^28-2^30 fill")
 
 
 @pytest.fixture(scope="session")

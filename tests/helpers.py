@@ -48,12 +48,16 @@ def ulp_distance(a, b):
     return np.abs(_ordered(a) - _ordered(b))
 
 
-def parity(got, want, max_ulp):
+def parity(got, want, max_ulp, exact=None):
     """Element-wise parity: returns (n_not_bit_identical, max ulp) and
-    asserts the ulp bound."""
+    asserts the ulp bound; where the boolean mask `exact` is set (outputs
+    on the fast path) the values must be bit-identical."""
     assert got.shape == want.shape and got.dtype == want.dtype
     it = np.int64 if got.dtype == np.float64 else np.int32
     diff = got.view(it) != want.view(it)
+    if exact is not None:
+        bad = int(np.count_nonzero(diff & exact))
+        assert bad == 0, "%d fast-path outputs are not bit-identical" % bad
     nd = int(np.count_nonzero(diff))
     mu = 0
     if nd:
