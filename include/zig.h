@@ -251,6 +251,21 @@ int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
 int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
                 double* sums, void* stream, const zig_launch* launch);
 
+/* zig_moments for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, result and summation order as zig_moments, but it calls
+ * no allocating routine: the partial sums live in a static device array
+ * of 4096 x 5 doubles (160 KB) that each GPU the library runs on holds
+ * until the process ends, and the tables must already be built on the
+ * current device (zig_build_tables(i_max) first, else ZIG_ESTATE).  The
+ * array holds the most workgroups one launch uses, so no n is refused on
+ * its account.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads, concurrent replays of
+ * a graph holding such a call) race and give wrong sums.  A capturing
+ * stream is accepted.  Errors: as zig_moments, plus ZIG_ESTATE. */
+int zig_moments_noalloc(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0,
+                        double p1, double* sums, void* stream, const zig_launch* launch);
+
 /* One request of a batch: dist ZIG_EXP (p0 = lambda) or ZIG_NORMAL (p0 = mu,
  * p1 = sigma), dtype, seed, first_index, n and a caller-owned device output
  * of n elements; the same contract as zig_fill for each request. */

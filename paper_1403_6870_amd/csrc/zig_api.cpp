@@ -419,6 +419,56 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   return ZIG_OK;
 }
 
+// Checked arguments of a moments call.
+struct MomentsCall {
+  double scale = 0.0, shift = 0.0;
+  uint32_t i_max = 256, spl = 32;
+  bool accel = false;
+};
+
+int moments_args(uint32_t dist, uint32_t dtype, uint64_t first_index, uint64_t n, double p0, double p1,
+                 const double* sums, const zig_launch* launch, MomentsCall* mc) {
+  if (dist > 1) return fail(ZIG_EINVAL, "unknown distribution");
+  if (dtype > 1) return fail(ZIG_EINVAL, "unknown dtype");
+  int r = check_params(dist, p0, p1, &mc->scale, &mc->shift);
+  if (r != ZIG_OK) return r;
+  zig_launch cfg = {0, 0, 0, 0};
+  if (launch) cfg = *launch;
+  mc->i_max = cfg.i_max ? cfg.i_max : 256;
+  if (!valid_imax(mc->i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 1024]");
+  if (cfg.flags & ZIG_LAUNCH_TRADITIONAL) return fail(ZIG_EINVAL, "the moments kernel runs the modified sampler only");
+  if (mc->i_max > kLdsLayers) return fail(ZIG_EINVAL, "the moments kernel takes i_max up to 256");
+  if (cfg.flags & ~ZIG_LAUNCH_NORMAL_ACCEL) return fail(ZIG_EINVAL, "unknown launch flags");
+  mc->spl = cfg.spl ? cfg.spl : 32;
+  if ((cfg.wg && cfg.wg != 256) || !moments_spl_supported(mc->spl))
+    return fail(ZIG_EINVAL, "the moments kernel runs 256 lanes x 16, 32 or 64 blocks");
+  mc->accel = dist == kDistNormal && (cfg.flags & ZIG_LAUNCH_NORMAL_ACCEL) != 0;
+  if (sums == nullptr) return fail(ZIG_EINVAL, "sums is null");
+  if (((uintptr_t)sums) % 8 != 0) return fail(ZIG_EINVAL, "sums is not 8-byte aligned");
+  if (n > 0 && n - 1 > UINT64_MAX - first_index) return fail(ZIG_EINVAL, "first_index + n exceeds 2^64");
+  return ZIG_OK;
+}
+
+int moments_zero(double* sums, void* stream) {
+  const int e = launch_moments_zero(sums, stream);
+  if (e != 0) return fail(ZIG_EHIP, std::string("moments launch: ") + hipGetErrorString((hipError_t)e));
+  return ZIG_OK;
+}
+
+// Device tables already built for the current device, without building or
+// allocating anything.
+int existing_device_tables(uint32_t i_max, const DevTable** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(std::make_pair(dev, i_max));
+  if (it == g_dev.end())
+    return fail(ZIG_ESTATE, "tables of this i_max are not built on this device: call zig_build_tables first");
+  *out = it->second;
+  return ZIG_OK;
+}
+
 // Argument block and launch of the moments kernels (shared by the
 // entry points with library-owned and with static scratch).
 int moments_launch(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double scale,
@@ -567,51 +617,48 @@ int zig_fill_trace(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
 int zig_moments(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0, double p1,
                 double* sums, void* stream, const zig_launch* launch) {
   zig::g_error.clear();
-  if (dist > 1) return zig::fail(ZIG_EINVAL, "unknown distribution");
-  if (dtype > 1) return zig::fail(ZIG_EINVAL, "unknown dtype");
-  double scale = 0.0, shift = 0.0;
-  int r = zig::check_params(dist, p0, p1, &scale, &shift);
+  zig::MomentsCall mc;
+  int r = zig::moments_args(dist, dtype, first_index, n, p0, p1, sums, launch, &mc);
   if (r != ZIG_OK) return r;
-  zig_launch cfg = {0, 0, 0, 0};
-  if (launch) cfg = *launch;
-  const uint32_t i_max = cfg.i_max ? cfg.i_max : 256;
-  if (!zig::valid_imax(i_max)) return zig::fail(ZIG_EINVAL, "i_max must be a power of two in [8, 1024]");
-  if (cfg.flags & ZIG_LAUNCH_TRADITIONAL)
-    return zig::fail(ZIG_EINVAL, "the moments kernel runs the modified sampler only");
-  if (i_max > zig::kLdsLayers) return zig::fail(ZIG_EINVAL, "the moments kernel takes i_max up to 256");
-  if (cfg.flags & ~ZIG_LAUNCH_NORMAL_ACCEL) return zig::fail(ZIG_EINVAL, "unknown launch flags");
-  const uint32_t spl = cfg.spl ? cfg.spl : 32;
-  if ((cfg.wg && cfg.wg != 256) || !zig::moments_spl_supported(spl))
-    return zig::fail(ZIG_EINVAL, "the moments kernel runs 256 lanes x 16, 32 or 64 blocks");
-  if (sums == nullptr) return zig::fail(ZIG_EINVAL, "sums is null");
-  if (((uintptr_t)sums) % 8 != 0) return zig::fail(ZIG_EINVAL, "sums is not 8-byte aligned");
-  if (n > 0 && n - 1 > UINT64_MAX - first_index) return zig::fail(ZIG_EINVAL, "first_index + n exceeds 2^64");
   bool capturing = false;
   r = zig::stream_capturing(stream, &capturing);
   if (r != ZIG_OK) return r;
   if (capturing)
     return zig::fail(ZIG_EINVAL, "zig_moments cannot be captured into a graph: its scratch slot would be fixed");
-  if (n == 0) {
-    const int e = zig::launch_moments_zero(sums, stream);
-    if (e != 0) return zig::fail(ZIG_EHIP, std::string("moments launch: ") + hipGetErrorString((hipError_t)e));
-    return ZIG_OK;
-  }
+  if (n == 0) return zig::moments_zero(sums, stream);
   const zig::DevTable* tabs = nullptr;
-  r = zig::device_tables(i_max, &tabs);
+  r = zig::device_tables(mc.i_max, &tabs);
   if (r != ZIG_OK) return r;
   zig::DeviceScratch* ds = nullptr;
   r = zig::device_scratch(&ds);
   if (r != ZIG_OK) return r;
-  const bool accel = (cfg.flags & ZIG_LAUNCH_NORMAL_ACCEL) != 0;
   int rr = ZIG_OK;
   const int e = zig::ring_launch(&ds->moments, stream, [&](void* partial) {
-    rr = zig::moments_launch(dist, dtype, seed, first_index, n, scale, shift, tabs, spl, accel,
+    rr = zig::moments_launch(dist, dtype, seed, first_index, n, mc.scale, mc.shift, tabs, mc.spl, mc.accel,
                              static_cast<double*>(partial), zig::kMomMaxGroups, sums, stream);
     return rr == ZIG_OK ? 0 : (int)hipErrorLaunchFailure;
   });
   if (rr != ZIG_OK) return rr;
   if (e != 0) return zig::fail(ZIG_EHIP, std::string("moments launch: ") + hipGetErrorString((hipError_t)e));
   return ZIG_OK;
+}
+
+int zig_moments_noalloc(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double p0,
+                        double p1, double* sums, void* stream, const zig_launch* launch) {
+  zig::g_error.clear();
+  zig::MomentsCall mc;
+  int r = zig::moments_args(dist, dtype, first_index, n, p0, p1, sums, launch, &mc);
+  if (r != ZIG_OK) return r;
+  if (n == 0) return zig::moments_zero(sums, stream);
+  const zig::DevTable* tabs = nullptr;
+  r = zig::existing_device_tables(mc.i_max, &tabs);
+  if (r != ZIG_OK) return r;
+  double* partial = nullptr;
+  const int e = zig::moments_static_scratch(&partial);
+  if (e != 0)
+    return zig::fail(ZIG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString((hipError_t)e));
+  return zig::moments_launch(dist, dtype, seed, first_index, n, mc.scale, mc.shift, tabs, mc.spl, mc.accel, partial,
+                             zig::kMomMaxGroups, sums, stream);
 }
 
 const char* zig_last_error(void) { return zig::g_error.c_str(); }

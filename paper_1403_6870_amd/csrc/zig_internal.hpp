@@ -139,6 +139,10 @@ constexpr uint32_t kMomMaxGroups = 4096;
 bool moments_spl_supported(uint32_t spl);
 int launch_moments(uint32_t dist, uint32_t dtype, uint32_t spl, const FillArgs& a, uint64_t tiles, double* partial,
                    uint32_t max_groups, double* sums, void* stream);
+// Device address of the file-scope partial-sum array of zig_moments_noalloc
+// (kMomMaxGroups * 5 doubles) on the current device, looked up once per
+// device.  Returns 0 or a hipError_t value.
+int moments_static_scratch(double** out);
 int launch_moments_zero(double* sums, void* stream);
 
 // One request of a batch as the batch kernel reads it (device memory).

@@ -356,7 +356,33 @@ int launch_d(uint32_t spl, const FillArgs& a, uint64_t tiles, double* partial, u
   return (int)hipErrorInvalidConfiguration;
 }
 
+// Partial sums for zig_moments_noalloc: one slot of 5 doubles per
+// workgroup, as many as a launch may use.  Host code must not pass this
+// name to a kernel (in host code it is a stand-in, not a device address);
+// it uses the address hipGetSymbolAddress gives on each device.
+static __device__ __align__(256) double scratch[kMomMaxGroups * 5];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+int moments_static_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    double* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
 
 bool moments_spl_supported(uint32_t spl) { return spl == 16 || spl == 32 || spl == 64; }
 

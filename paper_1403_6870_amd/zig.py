@@ -149,6 +149,8 @@ _server_stats = _sig("zig_server_stats_get", i32, [_srv_p, ctypes.POINTER(Server
 _server_replay = _sig("zig_server_replay", i32, [_srv_p, vp, u64, u32, vp])
 _server_destroy = _sig("zig_server_destroy", i32, [_srv_p])
 _moments = _sig("zig_moments", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp, ctypes.POINTER(Launch)])
+_moments_noalloc = _sig("zig_moments_noalloc", i32, [u32, u32, u64, u64, u64, dbl, dbl, vp, vp,
+                                                     ctypes.POINTER(Launch)])
 _last_error = _sig("zig_last_error", ctypes.c_char_p, [])
 _version = _sig("zig_version", ctypes.c_char_p, [])
 
@@ -253,6 +255,10 @@ def zig_fill_each(reqs, stream_ptr=None):
 
 def zig_moments(dist, dtype, seed, first_index, n, p0, p1, sums_ptr, stream_ptr=None, launch=None):
     _check(_moments(dist, dtype, seed, first_index, n, p0, p1, sums_ptr, stream_ptr, _launch(launch)))
+
+
+def zig_moments_noalloc(dist, dtype, seed, first_index, n, p0, p1, sums_ptr, stream_ptr=None, launch=None):
+    _check(_moments_noalloc(dist, dtype, seed, first_index, n, p0, p1, sums_ptr, stream_ptr, _launch(launch)))
 
 
 def zig_autotune(cache_path=None, flags=0):
