@@ -96,6 +96,17 @@ int zig_build_tables(uint32_t i_max);
  *             and of the concave ones (X_{j-1} <= 1), and the thresholds
  *             floor((1 - eps_cvx (1 + 2^-20)) 2^53) and
  *             ceil((1 + del_ccv (1 + 2^-20)) 2^53) on k1 + k2.
+ *   sq_lo, sq_hi  normal only (NULL for the exponential), L+1 entries,
+ *             index 0 unused: the squeeze of the plain box test of box j.
+ *             With k1, k2 its two 53-bit uniforms, k1 + k2 < sq_lo[j]
+ *             lies under the density and k1 + k2 >= sq_hi[j] over it, each
+ *             with a margin of 2^-20 of the box (or of its chord gap), so
+ *             the kernels decide such points without evaluating the
+ *             density and with the same outcome.  Convex boxes (X_j >= 1):
+ *             floor((1 - gap_j (1 + 2^-20)) 2^53) + 1 and 2^53 + 2^33;
+ *             concave ones (X_{j-1} <= 1): 2^53 - 2^33 and
+ *             ceil((1 + gap_j (1 + 2^-20)) 2^53); the box holding x = 1:
+ *             0 and 2^55 (never).
  * Builds the tables if needed.  Errors: ZIG_EINVAL, ZIG_ENOTABLES. */
 typedef struct {
   uint32_t dist, i_max, b, L;
@@ -113,6 +124,8 @@ typedef struct {
   double X0, invX0;
   double eps_cvx, del_ccv;
   uint64_t K_cvx, K_ccv;
+  const uint64_t* sq_lo;
+  const uint64_t* sq_hi;
 } zig_table_view;
 int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out);
 
@@ -291,8 +304,8 @@ typedef struct {
  * slots by a captured hipGraph (copy + kernel) that is replayed on `stream`;
  * `reqs` may be reused as soon as the call returns.  Outputs of different
  * requests must not overlap.  Requests with n = 0 are skipped; an invalid
- * request fails the whole call with ZIG_EINVAL (its index in the message)
- * before any device work. */
+ * request or an unknown flag fails the whole call with ZIG_EINVAL (a
+ * request's index in the message) before any device work. */
 int zig_fill_batch(const zig_request* reqs, uint32_t count, void* stream);
 int zig_fill_batch_ex(const zig_request* reqs, uint32_t count, void* stream, const zig_batch_opts* opts);
 

@@ -75,6 +75,19 @@ void to_device_layout(const HostTable& h, DevTable* d) {
     d->W[j] = h.W[j];
     d->H[j] = h.H[j];
   }
+  if (h.dist == kDistNormal) {
+    for (uint32_t j = 0; j <= h.L; ++j) {
+      d->SQlo[j] = h.SQlo[j];
+      d->SQhi[j] = h.SQhi[j];
+    }
+    // the fast-path table past the layers holds +inf for the normal: a
+    // slow output's placeholder is then +-inf and carries its sign to the
+    // slow path (NaN when its magnitude bits are all zero)
+    for (uint32_t i = h.L; i < h.i_max; ++i) {
+      d->XS[i] = HUGE_VAL;
+      d->XS32[i] = HUGE_VALF;
+    }
+  }
 }
 
 // device copy for the current device; returns the pair [exp, normal]
@@ -559,6 +572,8 @@ int zig_get_tables(uint32_t dist, uint32_t i_max, zig_table_view* out) {
   out->del_ccv = t.del_ccv;
   out->K_cvx = t.K_cvx;
   out->K_ccv = t.K_ccv;
+  out->sq_lo = t.SQlo.empty() ? nullptr : t.SQlo.data();
+  out->sq_hi = t.SQhi.empty() ? nullptr : t.SQhi.data();
   return ZIG_OK;
 }
 

@@ -165,6 +165,7 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
     flags = opts->flags;
   }
   if (!batch_shape_supported(wg, spl)) return fail(ZIG_EINVAL, "unsupported batch workgroup size / blocks per lane");
+  if (flags & ~ZIG_BATCH_NO_GRAPH) return fail(ZIG_EINVAL, "unknown batch flags");
   const uint64_t tile_blocks = (uint64_t)wg * spl;
 
   // descriptors into a temporary host array first (validation before any

@@ -80,6 +80,8 @@ struct TabView {
   uint32_t L, imask, b;
   uint64_t keps;
   uint64_t kcvx, kccv;  // normal: chord-band thresholds of the accelerated variant
+  const uint64_t* sqlo;  // normal: per-box squeeze of the plain box test
+  const uint64_t* sqhi;
   double X0, invX0;
 };
 
@@ -96,6 +98,8 @@ __device__ __forceinline__ TabView global_view(const DevTable* t) {
   v.keps = t->K_eps;
   v.kcvx = t->K_cvx;
   v.kccv = t->K_ccv;
+  v.sqlo = t->SQlo;
+  v.sqhi = t->SQhi;
   v.X0 = t->X0;
   v.invX0 = t->invX0;
   return v;
@@ -194,12 +198,19 @@ __device__ __forceinline__ double normal_slow(const TabView& N, const TabView& E
   const double base = N.f[j - 1], top = N.f[j];
   const double width = right - left, height = top - base;
   if constexpr (!ACCEL) {
+    // plain rejection; the squeeze decides most points as the density
+    // test would, so e^{-x^2/2} is evaluated only near the curve (tests
+    // counts every decision)
+    const uint64_t sq_lo = N.sqlo[j], sq_hi = N.sqhi[j];
     for (;;) {
       const uint64_t k1 = s.next() >> 11;
       const uint64_t k2 = s.next() >> 11;
       const double x = __builtin_fma(lattice53(k1), width, left);
-      const double yy = __builtin_fma(lattice53(k2), height, base);
       ++tests;
+      const uint64_t sum = k1 + k2;
+      if (sum < sq_lo) return x;
+      if (sum >= sq_hi) continue;
+      const double yy = __builtin_fma(lattice53(k2), height, base);
       if (yy < exp(-0.5 * (x * x))) return x;
     }
   }

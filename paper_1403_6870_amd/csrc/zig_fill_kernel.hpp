@@ -369,7 +369,15 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
     if constexpr (TRAD) {
       mag = dev::trad_slow<DIST>(c.tr, c.trex, g, c.k0, c.k1, neg, words, tests);
     } else {
-      if constexpr (DIST == kDistNormal) neg = dev::normal_sign<DT>(g, c.k0, c.k1, s32);
+      if constexpr (DIST == kDistNormal) {
+        // the placeholder is +-inf with the output's sign, or NaN when
+        // its magnitude bits were all zero (then the fast block is redone)
+        const OutT ph = *place;
+        if (__builtin_isnan(ph))
+          neg = dev::normal_sign<DT>(g, c.k0, c.k1, s32);
+        else
+          neg = __builtin_signbit(ph);
+      }
       mag = dev::slow_magnitude<DIST, ACCEL>(c.own, c.ex, g, c.k0, c.k1, region, words, tests);
     }
     OutT x = (OutT)mag;
@@ -430,11 +438,12 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   }
 }
 
-// Persistent workgroups: each takes `a.chunk` consecutive tiles per atomic
-// step of the per-stream counter (one atomic per tile would serialise the
-// device on that address), so the tiles in flight stay a window that
-// sweeps through the output in address order.  The last workgroup to leave
-// resets the counters for the next launch on the same stream.
+// Persistent workgroups.  A large fill gives them chunks of `a.chunk`
+// consecutive tiles per atomic step of its counter pair (one atomic per
+// tile would serialise the device on that address), so the tiles in flight
+// stay a window that sweeps through the output in address order and fast
+// workgroups take more; the last workgroup to leave resets the pair.  A
+// small fill (no counters) deals the tiles out round robin.
 template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
           bool WIDE = false>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(waves_hint(WG, S, !TRAD && !WIDE))))
@@ -453,26 +462,31 @@ fill_kernel(FillArgs a) {
   tl.stage = sh.stage;
   tl.slowmap = sh.slowmap;
   tl.prefix = sh.prefix;
-  if (a.counters == nullptr) {  // static schedule
-    __syncthreads();  // the tables in LDS are complete
-    for (uint64_t t = blockIdx.x; t < a.tiles; t += gridDim.x) {
-      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE>(a, c, tl, (uint32_t)t);
-      __syncthreads();
-    }
-    return;
-  }
+  // Tile schedule: with counters, chunks of a.chunk tiles taken from
+  // counters[0]; without, workgroup w takes tiles w, w + G, ...
+  const bool dynamic = a.counters != nullptr;
+  uint64_t next = blockIdx.x;
+  if (!dynamic) __syncthreads();  // the tables in LDS are complete
   for (;;) {
-    if (threadIdx.x == 0) sh.tile = atomicAdd(&a.counters[0], 1u);
-    __syncthreads();
-    const uint64_t t0 = (uint64_t)sh.tile * a.chunk;
+    uint64_t t0, t1;
+    if (dynamic) {
+      if (threadIdx.x == 0) sh.tile = atomicAdd(&a.counters[0], 1u);
+      __syncthreads();
+      t0 = (uint64_t)sh.tile * a.chunk;
+      t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
+    } else {
+      t0 = next;
+      t1 = next + 1;
+      next += gridDim.x;
+    }
     if (t0 >= a.tiles) break;
-    const uint64_t t1 = t0 + a.chunk < a.tiles ? t0 + a.chunk : a.tiles;
     for (uint64_t t = t0; t < t1; ++t) {
       fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE>(a, c, tl, (uint32_t)t);
       __syncthreads();
     }
   }
-  if (threadIdx.x == 0) {
+  // the last workgroup to leave resets the counters for the slot's next user
+  if (dynamic && threadIdx.x == 0) {
     if (atomicAdd(&a.counters[1], 1u) == gridDim.x - 1) {
       atomicExch(&a.counters[0], 0u);
       atomicExch(&a.counters[1], 0u);

@@ -33,10 +33,15 @@ struct DevTable {
   double H[kMaxLayers + 1];
   uint64_t T[kMaxLayers];
   uint32_t A[kMaxLayers];
+  // normal: per-box squeeze of the plain box test on k1 + k2 (the two
+  //53-bit uniforms): below SQlo[j] the point is under the density, at or
+  // above SQhi[j] it is over it, both with a margin far beyond rounding
+  uint64_t SQlo[kMaxLayers + 1];
+  uint64_t SQhi[kMaxLayers + 1];
 };
 
 // g++ builds the host side and hipcc the device side: both must agree
-static_assert(sizeof(DevTable) == 57432, "DevTable layout");
+static_assert(sizeof(DevTable) == 57432 + 2 * 8 * (kMaxLayers + 1), "DevTable layout");
 
 // Host copy with the same content plus the quantities only tests need.
 struct HostTable {
@@ -49,6 +54,7 @@ struct HostTable {
   uint64_t K_eps = 0;
   double eps_cvx = 0.0, del_ccv = 0.0;  // normal only
   uint64_t K_cvx = 0, K_ccv = 0;
+  std::vector<uint64_t> SQlo, SQhi;  // normal only, index j = 1..L
 };
 
 // Builds one distribution's tables in binary128 (zig_tables.cpp).

@@ -234,8 +234,20 @@ std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out) {
   // above, the cap included), at the point where the curve's normalised
   // slope is -1: x e^{-x^2/2} = h / w.  Each is widened by 2^-20 and turned
   // into a threshold on k1 + k2.
+  //
+  // The same gaps box by box give the squeeze of the plain box test (it
+  // decides the same points as the density test, only without evaluating
+  // it): in a convex box the point is under the curve when
+  // u + v <= 1 - gap_j (1 + 2^-20) and over it when u + v >= 1 + 2^-20; in a
+  // concave box under it when u + v < 1 - 2^-20 and over it when
+  // u + v >= 1 + gap_j (1 + 2^-20).  The margins (2^-20 of the box, or of
+  // its gap) exceed by far the rounding of the computed test; the box
+  // holding x = 1 is never squeezed.
   if (dist == kDistNormal) {
     q128 widest_below = 0, widest_above = 0;
+    const uint64_t one53 = (uint64_t)1 << 53, margin = (uint64_t)1 << 33;
+    t.SQlo.assign(L + 1, 0);
+    t.SQhi.assign(L + 1, (uint64_t)1 << 55);
     for (uint32_t j = 1; j <= L; ++j) {
       const bool convex = t.X[j] >= 1.0, concave = t.X[j - 1] <= 1.0;
       if (!convex && !concave) continue;
@@ -248,6 +260,15 @@ std::string build_host_table(uint32_t dist, uint32_t i_max, HostTable* out) {
       const q128 u = (xs - left) / w, c = (P.p(xs) - base) / h;
       if (convex) widest_below = fmaxq(widest_below, (1 - u) - c);
       if (concave) widest_above = fmaxq(widest_above, c - (1 - u));
+      const q128 gap = convex ? (1 - u) - c : c - (1 - u);
+      const q128 wide_gap = gap * (1 + 0x1p-20Q);
+      if (convex) {
+        t.SQlo[j] = (uint64_t)floorq((1 - wide_gap) * 9007199254740992.0Q) + 1;
+        t.SQhi[j] = one53 + margin;
+      } else {
+        t.SQlo[j] = one53 - margin;
+        t.SQhi[j] = (uint64_t)ceilq((1 + wide_gap) * 9007199254740992.0Q);
+      }
     }
     const q128 widen = 1 + 0x1p-20Q;
     t.eps_cvx = (double)widest_below;

@@ -39,7 +39,8 @@ class TableView(ctypes.Structure):
                 ("XS32", ctypes.POINTER(ctypes.c_float)), ("W", ctypes.POINTER(dbl)), ("H", ctypes.POINTER(dbl)),
                 ("q", ctypes.POINTER(u64)), ("T", ctypes.POINTER(u64)), ("alias", ctypes.POINTER(u32)),
                 ("eps", dbl), ("K_eps", u64), ("X0", dbl), ("invX0", dbl),
-                ("eps_cvx", dbl), ("del_ccv", dbl), ("K_cvx", u64), ("K_ccv", u64)]
+                ("eps_cvx", dbl), ("del_ccv", dbl), ("K_cvx", u64), ("K_ccv", u64),
+                ("sq_lo", ctypes.POINTER(u64)), ("sq_hi", ctypes.POINTER(u64))]
 
 
 class TradView(ctypes.Structure):
@@ -201,6 +202,8 @@ def zig_get_tables(dist, i_max=256):
         "q": arr(v.q, L + 1, np.uint64), "T": arr(v.T, im, np.uint64), "A": arr(v.alias, im, np.uint32),
         "eps": v.eps, "K_eps": int(v.K_eps), "X0": v.X0, "invX0": v.invX0,
         "eps_cvx": v.eps_cvx, "del_ccv": v.del_ccv, "K_cvx": int(v.K_cvx), "K_ccv": int(v.K_ccv),
+        "sq_lo": arr(v.sq_lo, L + 1, np.uint64) if v.sq_lo else None,
+        "sq_hi": arr(v.sq_hi, L + 1, np.uint64) if v.sq_hi else None,
     }
 
 

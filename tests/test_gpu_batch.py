@@ -159,3 +159,12 @@ def test_batch_invalid_request_rejected(env):
     with pytest.raises(zig.ZigError) as e:
         zig.zig_fill_batch(arr, torch.cuda.current_stream().cuda_stream)
     assert e.value.status == zig.ZIG_EINVAL and "request 1" in str(e.value)
+
+
+def test_batch_unknown_flag_rejected(env):
+    torch, zig = env
+    o = torch.empty(10, dtype=torch.float64, device="cuda")
+    arr = (zig.Request * 1)(zig.Request(0, 0, 1, 0, 10, 1.0, 0.0, o.data_ptr()))
+    with pytest.raises(zig.ZigError) as e:
+        zig.zig_fill_batch(arr, torch.cuda.current_stream().cuda_stream, {"flags": 4})
+    assert e.value.status == zig.ZIG_EINVAL

@@ -9,6 +9,8 @@ import re
 import numpy as np
 import pytest
 
+from helpers import EXP, NORMAL
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "zig.h")
 
@@ -141,3 +143,47 @@ def test_autotune_bad_flags_refused_before_device_work():
         with pytest.raises(zig.ZigError) as e:
             zig.zig_autotune(None, flags)
         assert e.value.status == zig.ZIG_EINVAL
+
+
+@pytest.mark.parametrize("i_max", [8, 256, 1024])
+def test_normal_box_squeeze_agrees_with_density_test(zig, O, i_max):
+    """The library's per-box squeeze of the plain normal box test decides
+    points without evaluating the density: every point it calls accepted
+    (k1 + k2 < sq_lo) the oracle's density test accepts, and every point it
+    calls rejected (k1 + k2 >= sq_hi) the test rejects: probed along both
+    boundaries and at random inside both regions, in every box."""
+    t = zig.zig_get_tables(NORMAL, i_max)
+    assert zig.zig_get_tables(EXP, i_max)["sq_lo"] is None
+    L, X = t["L"], t["X"]
+    lo, hi = t["sq_lo"].astype(object), t["sq_hi"].astype(object)
+    one53, top = 2 ** 53, 2 ** 53 - 1
+    rng = np.random.default_rng(i_max)
+    decided = []
+
+    def probe(total, want, j):
+        a, b = max(0, total - top), min(total, top)
+        if a > b:
+            return
+        ks = {a, b} | {int(v) for v in np.linspace(a, b, 33)} | {int(v) for v in rng.integers(a, b + 1, 16)}
+        for k1 in ks:
+            got, _ = O.box_attempt(NORMAL, i_max, j, k1, total - k1)
+            assert got == want, (j, k1, total - k1, want)
+
+    for j in range(1, L + 1):
+        convex, concave = X[j] >= 1.0, X[j - 1] <= 1.0
+        if convex:
+            assert hi[j] == one53 + 2 ** 33 and lo[j] < one53
+        elif concave:
+            assert lo[j] == one53 - 2 ** 33 and hi[j] > one53
+        else:
+            assert lo[j] == 0 and hi[j] == 2 ** 55
+            continue
+        probe(lo[j] - 1, True, j)
+        probe(hi[j], False, j)
+        for _ in range(8):
+            probe(int(rng.integers(0, lo[j])), True, j)
+            probe(int(rng.integers(hi[j], 2 * top + 1)), False, j)
+        # share of the box the squeeze decides (area under u + v = s is s^2 / 2)
+        s_lo, s_hi = lo[j] / one53, hi[j] / one53
+        decided.append(s_lo * s_lo / 2 + (2 - s_hi) ** 2 / 2)
+    assert np.mean(decided) > 0.8
