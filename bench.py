@@ -245,7 +245,7 @@ def serve_bench(torch, zig, seconds):
                        "N(N(0,1), U[0.1,5]), FP32/FP64 50/50, 64 clients (seed 1000 + id), 16 GiB admission "
                        "cap, 4 fill streams (numpy default_rng(5))",
            "latency": "host time the completion is observed minus the scheduled arrival"}
-    for name, rate, secs in [("rate_20k", 20000.0, seconds), ("rate_200k", 200000.0, max(1.0, seconds / 5))]:
+    for name, rate, secs in [("rate_20k", 20000.0, seconds), ("rate_200k", 200000.0, min(2.0, seconds))]:
         tr = c5_trace(zig, secs, rate)
         offered = float(tr["n"].sum()) / secs / 1e9
         log("serve %s: %d requests over %.1f s (offered %.1f Gsamples/s)" % (name, len(tr), secs, offered))
@@ -365,12 +365,25 @@ def autotune_report(zig):
     return {"seconds": round(secs, 2), "fill": rows, "batch": c["batch"]}
 
 
+def cpu_model():
+    """The host CPU's model line from /proc/cpuinfo (empty if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def cpu_baseline():
     """The oracle on the host cores, about 10-15 s of work: the first 2^32
-    outputs of each headline stream on all threads (in chunks of 2^26, so
-    host memory stays small), and the first 2^26 of each on one thread."""
+    outputs of each headline stream on every core this process may run on
+    (in chunks of 2^26, so host memory stays small), and the first 2^26 of
+    each on one thread."""
     from oracle import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = max(1, len(os.sched_getaffinity(0)))
     chunk = 1 << 26
 
     def run(n, nthreads):
@@ -385,6 +398,7 @@ def cpu_baseline():
     t_one = run(n_one, 1)
     return {
         "value": round(2 * n_all / t_all / 1e9, 5), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+        "nproc": os.cpu_count(), "cpu_model": cpu_model(),
         "sample": "2^32 Exp(2.5) + 2^32 N(-1,3) FP64 outputs (indices 0..2^32-1 of the benchmark streams, "
                   "chunks of 2^26), %d threads over contiguous index ranges, %.1f s" % (threads, t_all),
         "single_thread": {"value": round(2 * n_one / t_one / 1e9, 5), "unit": "Gsamples/s",
@@ -399,8 +413,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the 20k requests/s serving trace (the 200k/s trace runs a fifth of it)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the 20k requests/s serving trace (the 200k/s trace runs 2 s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (a kernel of known traffic, for scaling the "
                          "HBM byte counters of a profiler run)")

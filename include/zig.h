@@ -302,7 +302,9 @@ typedef struct {
  * counter.  Each request's output is bit-identical to zig_fill of the same
  * request.  The request descriptors are copied from a ring of pinned host
  * slots by a captured hipGraph (copy + kernel) that is replayed on `stream`;
- * `reqs` may be reused as soon as the call returns.  Outputs of different
+ * a batch of at most 8 requests instead passes them in the kernel
+ * arguments and is launched directly.  `reqs` may be reused as soon as the
+ * call returns.  Outputs of different
  * requests must not overlap.  Requests with n = 0 are skipped; an invalid
  * request or an unknown flag fails the whole call with ZIG_EINVAL (a
  * request's index in the message) before any device work. */

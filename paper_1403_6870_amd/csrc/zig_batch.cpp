@@ -224,7 +224,11 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   const uint32_t chunk = batch_chunk(total, tile_blocks, groups);
   const uint32_t grid = groups;
 
-  BatchHeader* h = static_cast<BatchHeader*>(s.host);
+  // a batch of a few requests passes its descriptors in the kernel
+  // arguments and is launched directly: no copy, no graph
+  const bool inline_desc = m <= kInlineReqs;
+  BatchInline inl;
+  BatchHeader* h = inline_desc ? &inl.hdr : static_cast<BatchHeader*>(s.host);
   std::memset(h, 0, sizeof(*h));
   h->count = m;
   h->total_tiles = (uint32_t)total;
@@ -239,7 +243,10 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   ba.seed_base = 0;
   hipStream_t st = static_cast<hipStream_t>(stream);
 
-  if (flags & ZIG_BATCH_NO_GRAPH) {
+  if (inline_desc) {
+    const int le = launch_batch_inline(wg, spl, full, grid, ba, inl, stream);
+    if (le != 0) return hip_fail("batch launch", (hipError_t)le);
+  } else if (flags & ZIG_BATCH_NO_GRAPH) {
     e = hipMemcpyAsync(s.dev, s.host, sizeof(BatchHeader) + (size_t)m * sizeof(BatchReq), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail("hipMemcpyAsync(batch)", e);
     int le = launch_batch(wg, spl, full, grid, ba, stream);

@@ -65,7 +65,7 @@ __device__ __forceinline__ uint32_t find_request(const BatchReq* reqs, uint32_t 
 }
 
 template <int WG, int S, bool FULL>
-__global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
+__device__ __forceinline__ void batch_body(const BatchArgs& ba, const BatchHeader* hdr) {
   __shared__ BatchLds<WG, S, FULL> sh;
   const uint32_t tid = threadIdx.x;
   for (uint32_t d = 0; d < 2; ++d) {
@@ -104,10 +104,10 @@ __global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
   tl.slowmap = sh.slowmap;
   tl.prefix = sh.prefix;
 
-  const uint32_t count = ba.hdr->count;
-  const uint32_t total = ba.hdr->total_tiles;
-  const uint32_t step = ba.hdr->chunk;
-  const BatchReq* reqs = reinterpret_cast<const BatchReq*>(ba.hdr + 1);
+  const uint32_t count = hdr->count;
+  const uint32_t total = hdr->total_tiles;
+  const uint32_t step = hdr->chunk;
+  const BatchReq* reqs = reinterpret_cast<const BatchReq*>(hdr + 1);
 
   for (;;) {
     if (tid == 0) sh.chunk = atomicAdd(&ba.counters[0], 1u);
@@ -193,6 +193,18 @@ __global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
   }
 }
 
+template <int WG, int S, bool FULL>
+__global__ void __launch_bounds__(WG) batch_kernel(BatchArgs ba) {
+  batch_body<WG, S, FULL>(ba, ba.hdr);
+}
+
+// A small batch with its descriptors in the kernel arguments: read in
+// place from the argument segment, no copy to device memory first.
+template <int WG, int S, bool FULL>
+__global__ void __launch_bounds__(WG) batch_kernel_inline(BatchArgs ba, BatchInline inl) {
+  batch_body<WG, S, FULL>(ba, &inl.hdr);
+}
+
 template <class K>
 int groups_of(K kernel, int wg, uint32_t* out) {
   static std::mutex mu;
@@ -254,6 +266,37 @@ int launch_batch(uint32_t wg, uint32_t spl, bool full, uint32_t grid, const Batc
   ZIG_BATCH_SHAPES(ZIG_B)
 #undef ZIG_B
   return (int)hipErrorInvalidConfiguration;
+}
+
+int launch_batch_inline(uint32_t wg, uint32_t spl, bool full, uint32_t grid, const BatchArgs& a,
+                        const BatchInline& inl, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+#define ZIG_B(W, S_)                                                                                 \
+  if (wg == W && spl == S_) {                                                                        \
+    if (full)                                                                                        \
+      hipLaunchKernelGGL((batch_kernel_inline<W, S_, true>), dim3(grid), dim3(W), 0, st, a, inl);  \
+    else                                                                                             \
+      hipLaunchKernelGGL((batch_kernel_inline<W, S_, false>), dim3(grid), dim3(W), 0, st, a, inl); \
+    return (int)hipGetLastError();                                                                   \
+  }
+  ZIG_BATCH_SHAPES(ZIG_B)
+#undef ZIG_B
+  return (int)hipErrorInvalidConfiguration;
+}
+
+namespace {
+__global__ void raise_counters_kernel(uint64_t* counters, const uint64_t* ends, uint32_t count) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < count && ends[c] != 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(&counters[c]), (unsigned long long)ends[c]);
+}
+}  // namespace
+
+int launch_raise_counters(uint64_t* counters, const uint64_t* ends, uint32_t count, void* stream) {
+  if (count == 0) return 0;
+  hipLaunchKernelGGL(raise_counters_kernel, dim3((count + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     counters, ends, count);
+  return (int)hipGetLastError();
 }
 
 }  // namespace zig

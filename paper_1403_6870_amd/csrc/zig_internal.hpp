@@ -181,6 +181,19 @@ struct BatchArgs {
   uint64_t seed_base;
 };
 
+// A small batch whose header and requests travel in the kernel arguments
+// (no descriptor copy): the requests follow the header as in device memory.
+constexpr uint32_t kInlineReqs = 8;
+struct BatchInline {
+  BatchHeader hdr;
+  BatchReq reqs[kInlineReqs];
+};
+static_assert(sizeof(BatchInline) == 16 + 104 * kInlineReqs, "BatchInline layout");
+
+// counters[c] = max(counters[c], ends[c]) for c < count, on `stream`: the
+// owed client counter raises of served requests that ran as plain fills.
+int launch_raise_counters(uint64_t* counters, const uint64_t* ends, uint32_t count, void* stream);
+
 // Descriptor of one checked request with n > 0; the tile fields are left
 // for the caller, which knows the tile size (zig_batch.cpp).
 void make_descriptor(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double scale,
@@ -194,6 +207,9 @@ uint32_t batch_chunk(uint64_t total_tiles, uint32_t tile_blocks, uint32_t groups
 // `full` selects the variant that stages every table in LDS (see
 // batch_full); batch_groups gives each variant's resident count.
 int launch_batch(uint32_t wg, uint32_t spl, bool full, uint32_t grid, const BatchArgs& a, void* stream);
+// The same with the descriptors in the kernel arguments (a.hdr unused).
+int launch_batch_inline(uint32_t wg, uint32_t spl, bool full, uint32_t grid, const BatchArgs& a,
+                        const BatchInline& inl, void* stream);
 
 int batch_groups(uint32_t wg, uint32_t spl, bool full, uint32_t* groups);
 
@@ -201,6 +217,12 @@ int batch_groups(uint32_t wg, uint32_t spl, bool full, uint32_t* groups);
 // resident workgroups busy for a few tiles each (zig_batch.cpp).
 bool batch_full(uint64_t total_tiles, uint32_t lean_groups);
 bool batch_shape_supported(uint32_t wg, uint32_t spl);
+
+// zig_fill with the fixed tile schedule at every size (no counter slot,
+// so no event waits between streams): for callers that keep many fills
+// queued on several streams of their own (zig_api.cpp).
+int fill_static(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0, double p1,
+                void* out, void* stream);
 
 // Shared helpers of the C ABI implementation (zig_api.cpp).
 int device_tables_for(uint32_t i_max, const DevTable** out);

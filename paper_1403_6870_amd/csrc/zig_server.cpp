@@ -1,21 +1,28 @@
 // Serving loop: continuous batching of fill requests.
 //
-//   submit -> FIFO intake -> scheduler thread: admission against the output
-//   arena (first fit, in arrival order, so a client's requests keep their
-//   order), first indices from the client counters in admission order,
-//   batch descriptors -> one batch per free (stream, slot), all on that
-//   fill stream: copy of the descriptors, the persistent batch kernel
-//   (whose last workgroup raises the device-resident client counters to
-//   the batch's ends), optional copies of outputs -> completion thread:
-//   polls the batches' events, stamps the completions, wakes waiters.
+//   submit -> FIFO intake -> scheduler thread (spinning briefly on a work
+//   counter before it parks, so a request is taken up in about a
+//   microsecond): admission against the output arena (first fit, in
+//   arrival order, so a client's requests keep their order), first indices
+//   from the client counters in admission order, one batch per free
+//   (stream, slot), all on that fill stream -> completion thread: polls the
+//   batches' events, stamps the completions, wakes waiters.
+//   A batch of one request runs as that request's plain fill; a batch of a
+//   few requests passes its descriptors in the kernel arguments of the
+//   batch kernel; a larger one copies them to the device first.  The batch
+//   kernel's last workgroup raises the device-resident client counters to
+//   the batch's ends; a plain fill's raise is owed and made in bulk before
+//   the counters are next read.  Optional copies of outputs follow on the
+//   same stream.
 //
-// The indices are fixed on the host when a request is admitted (a mirror
-// of the device counters, advanced by the same rule), so batches on
-// different fill streams need no ordering among themselves: a request's
-// samples are the same whether it ran alone or in any mix.  The device
-// counters end at the same values whatever order the batches finish in (a
-// max of increasing ends); they are what a checkpoint reads.  A request
-// whose indices would pass 2^64 - 2 is rejected at admission.
+// The host mirror of the client counters decides every first index, at
+// admission and in admission order, so batches on different fill streams
+// need no ordering among themselves and a request's samples are the same
+// whether it ran alone or in any mix.  The device counters are its
+// persistent copy: they end at the same values whatever order the batches
+// finish in (a max of increasing ends), and they are what a checkpoint
+// reads.  A request whose indices would pass 2^64 - 2 is rejected at
+// admission.
 //
 // The host fake backend makes no device call: it writes first_index + k as
 // the k-th output into a host arena after an optional delay, and can fail
@@ -23,6 +30,7 @@
 // others are unaffected).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -44,6 +52,7 @@ namespace zig {
 namespace {
 
 constexpr uint32_t kServeMaxBatch = 4096;  // requests per batch
+constexpr uint64_t kSchedSpinNs = 200000;  // the scheduler spins this long before parking
 
 uint64_t now_ns() {
   return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -158,6 +167,7 @@ struct DevSlot {
 struct Item {
   uint32_t client, dist, dtype;
   uint64_t n, first;
+  double p0, p1;  // as submitted (lambda, or mu and sigma)
   double scale, shift;
   void* out;
   void* copy_to;
@@ -199,7 +209,12 @@ struct Server {
   std::condition_variable cv_sched, cv_done, cv_inflight;
   std::deque<Pending> intake;
   std::unordered_map<uint64_t, Ticket> tickets;
-  std::vector<uint64_t> next_host;  // host mirror of the client counters
+  std::vector<uint64_t> next_host;  // host mirror of the client counters (decides first indices)
+  // Client counter raises owed by requests that ran as plain fills: the
+  // device copy catches up in bulk before it is read (raise_dev stages them).
+  std::vector<uint64_t> owed;
+  bool any_owed = false;
+  uint64_t* raise_dev = nullptr;
   Arena arena;
   uint64_t queued_bytes = 0;
   uint64_t next_ticket = 1, next_batch = 1;
@@ -210,11 +225,21 @@ struct Server {
   int broken = ZIG_OK;  // a device step failed: the server accepts no more work
   bool replaying_naive = false;
   std::atomic<bool> stop{false};
+  // bumped with every change the scheduler may be waiting for (new
+  // request, free slot, free arena space); it watches it while it spins
+  std::atomic<uint64_t> work_epoch{0};
   bool stop_completers = false;  // set once the scheduler has exited
   std::thread sched;
   std::vector<std::thread> completers;  // one per fill stream
   zig_server_stats stats;
 };
+
+// Tells the scheduler (spinning or parked) that something it waits for
+// changed; caller holds mu.  Cheap when no thread is parked on cv_sched.
+void wake_sched(Server* s) {
+  s->work_epoch.fetch_add(1, std::memory_order_release);
+  s->cv_sched.notify_all();
+}
 
 namespace {
 
@@ -236,11 +261,50 @@ bool free_slot(Server* s, int* stream, int* slot) {
   return false;
 }
 
+// A batch of one request runs as the plain fill of that request (the
+// kernel a lone request is fastest with) and its completion event is
+// recorded right after it; the raise of its client's device counter is
+// owed and made in bulk before the counters are next read.
+int launch_single(Server* s, Batch* b) {
+  DevSlot& d = s->slots[b->stream][b->slot];
+  const Item& it = b->items[0];
+  hipStream_t fs = s->fill_streams[b->stream];
+  int r = fill_static(it.dist, it.dtype, s->cfg.seed_base + it.client, it.first, it.n, it.p0, it.p1, it.out, fs);
+  if (r != ZIG_OK) return fail(ZIG_EHIP, std::string("serve: fill: ") + zig_last_error());
+  hipError_t e = hipSuccess;
+  if (it.copy_to) {
+    e = hipMemcpyAsync(it.copy_to, it.out, it.n * (it.dtype == ZIG_F64 ? 8 : 4), hipMemcpyDeviceToDevice, fs);
+    if (e != hipSuccess) return fail(ZIG_EHIP, std::string("serve: output copy: ") + hipGetErrorString(e));
+  }
+  e = hipEventRecord(d.ev_done, fs);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("serve: completion record: ") + hipGetErrorString(e));
+  return ZIG_OK;
+}
+
+// Makes the owed counter raises (caller holds mu, no launch in progress):
+// stages the owed ends and raises the device counters to them on fill
+// stream 0.
+int pay_owed_locked(Server* s) {
+  if (!s->any_owed) return ZIG_OK;
+  hipError_t e = hipMemcpy(s->raise_dev, s->owed.data(), s->cfg.clients * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("counter raise: ") + hipGetErrorString(e));
+  const int le = launch_raise_counters(s->counters_dev, s->raise_dev, s->cfg.clients, s->fill_streams[0]);
+  if (le != 0) return fail(ZIG_EHIP, std::string("counter raise: ") + hipGetErrorString((hipError_t)le));
+  std::fill(s->owed.begin(), s->owed.end(), 0);
+  s->any_owed = false;
+  return ZIG_OK;
+}
+
 int launch_device(Server* s, Batch* b) {
+  if (b->items.size() == 1) return launch_single(s, b);
   DevSlot& d = s->slots[b->stream][b->slot];
   const uint32_t m = (uint32_t)b->items.size();
   const uint32_t tile_blocks = s->wg * s->spl;
-  BatchHeader* h = static_cast<BatchHeader*>(d.desc_host);
+  // a batch of a few requests passes its descriptors in the kernel
+  // arguments: no copy to the device ahead of the kernel
+  const bool inline_desc = m <= kInlineReqs;
+  BatchInline inl;
+  BatchHeader* h = inline_desc ? &inl.hdr : static_cast<BatchHeader*>(d.desc_host);
   BatchReq* q = reinterpret_cast<BatchReq*>(h + 1);
   uint64_t total = 0;
   for (uint32_t i = 0; i < m; ++i) {
@@ -259,9 +323,12 @@ int launch_device(Server* s, Batch* b) {
   const uint32_t groups = full ? s->groups_full : s->groups;
   h->chunk = batch_chunk(total, tile_blocks, groups);
   hipStream_t fs = s->fill_streams[b->stream];
-  hipError_t e = hipMemcpyAsync(d.desc_dev, d.desc_host, sizeof(BatchHeader) + (size_t)m * sizeof(BatchReq),
-                                hipMemcpyHostToDevice, fs);
-  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("serve: descriptor copy: ") + hipGetErrorString(e));
+  hipError_t e = hipSuccess;
+  if (!inline_desc) {
+    e = hipMemcpyAsync(d.desc_dev, d.desc_host, sizeof(BatchHeader) + (size_t)m * sizeof(BatchReq),
+                       hipMemcpyHostToDevice, fs);
+    if (e != hipSuccess) return fail(ZIG_EHIP, std::string("serve: descriptor copy: ") + hipGetErrorString(e));
+  }
   BatchArgs ba;
   ba.hdr = static_cast<const BatchHeader*>(d.desc_dev);
   ba.tabs = s->tabs;
@@ -272,7 +339,8 @@ int launch_device(Server* s, Batch* b) {
   // (and retires) a few workgroups instead of every resident one
   const uint64_t steps = (total + h->chunk - 1) / h->chunk;
   const uint32_t grid = steps < (uint64_t)groups ? (uint32_t)steps : groups;
-  const int le = launch_batch(s->wg, s->spl, full, grid, ba, fs);
+  const int le = inline_desc ? launch_batch_inline(s->wg, s->spl, full, grid, ba, inl, fs)
+                             : launch_batch(s->wg, s->spl, full, grid, ba, fs);
   if (le != 0) return fail(ZIG_EHIP, std::string("serve: batch launch: ") + hipGetErrorString((hipError_t)le));
   for (const Item& it : b->items) {
     if (!it.copy_to) continue;
@@ -337,16 +405,138 @@ void cancel_queued_locked(Server* s, int status) {
   s->cv_done.notify_all();
 }
 
+// Forms one batch from the head of the intake on (stream k, slot j), both
+// free, and launches it (the HIP calls outside mu).  Called by the
+// scheduler thread, holding mu through lk.
+void form_and_launch(Server* s, std::unique_lock<std::mutex>& lk, int k, int j) {
+  Batch* b = new Batch();
+  b->id = s->next_batch++;
+  b->stream = k;
+  b->slot = j;
+  const uint64_t t_admit = now_ns();
+  bool rejected = false;
+  while (!s->intake.empty() && b->items.size() < s->cfg.max_batch) {
+    Pending& p = s->intake.front();
+    uint64_t off;
+    if (!s->arena.alloc(p.bytes, &off)) break;  // FIFO: later requests wait too
+    Ticket& tk = s->tickets[p.ticket];
+    uint64_t& next = s->next_host[p.client];
+    int st = ZIG_OK;
+    if (p.spec.n > UINT64_MAX - next)  // indices up to 2^64 - 2, so a counter never wraps
+      st = ZIG_EINVAL;
+    else if (!s->device && s->cfg.fake_fail_every && ++s->fake_seen % s->cfg.fake_fail_every == 0)
+      st = ZIG_EHIP;
+    if (st != ZIG_OK) {  // completes now, uses no index
+      s->arena.release(off, p.bytes);
+      tk.comp.t_admit_ns = tk.comp.t_launch_ns = t_admit;
+      s->stats.failed_requests += 1;
+      s->queued_bytes -= Arena::round(p.bytes);
+      const uint64_t id = p.ticket;
+      s->intake.pop_front();
+      complete_locked(s, id, st, t_admit);
+      rejected = true;
+      continue;
+    }
+    tk.off = off;
+    tk.bytes = p.bytes;
+    tk.state = kLaunched;
+    tk.comp.t_admit_ns = t_admit;
+    tk.comp.out = arena_base(s) + off;
+    tk.comp.batch_id = b->id;
+    tk.comp.first_index = next;
+    Item item;
+    item.client = p.client;
+    item.dist = p.spec.dist;
+    item.dtype = p.spec.dtype;
+    item.n = p.spec.n;
+    item.first = next;
+    item.p0 = p.spec.p0;
+    item.p1 = p.spec.p1;
+    item.scale = p.scale;
+    item.shift = p.shift;
+    item.out = tk.comp.out;
+    item.copy_to = tk.copy_to;
+    next += p.spec.n;
+    b->items.push_back(item);
+    b->tickets.push_back(p.ticket);
+    s->queued_bytes -= Arena::round(p.bytes);
+    s->intake.pop_front();
+  }
+  if (rejected) s->cv_done.notify_all();
+  if (b->items.empty()) {
+    delete b;
+    return;
+  }
+  b->status.assign(b->items.size(), ZIG_OK);
+  s->slots[k][j].busy = true;
+  s->next_stream = (k + 1) % (int)s->cfg.streams;
+  const uint64_t t_launch = now_ns();
+  for (uint64_t tid : b->tickets) {
+    Ticket& tk = s->tickets[tid];
+    tk.comp.batch_size = (uint32_t)b->items.size();
+    tk.comp.t_launch_ns = t_launch;
+  }
+  s->stats.batches += 1;
+  s->stats.requests += b->items.size();
+  for (const Item& it : b->items) s->stats.samples += it.n;
+  if (s->arena.used() > s->stats.max_bytes_in_use) s->stats.max_bytes_in_use = s->arena.used();
+  s->inflight_count += 1;
+  if (s->inflight_count > s->stats.max_inflight_batches) s->stats.max_inflight_batches = s->inflight_count;
+  if (s->device) {
+    // The slot is ours and the indices are fixed: launch without the lock,
+    // so submitters and completions are not held up by the HIP calls.
+    s->launching += 1;
+    lk.unlock();
+    const int st = launch_device(s, b);
+    lk.lock();
+    s->launching -= 1;
+    b->launch_status = st;
+    if (st == ZIG_OK && b->items.size() == 1) {  // ran as a plain fill: its counter raise is owed
+      const Item& it = b->items[0];
+      uint64_t& o = s->owed[it.client];
+      if (it.first + it.n > o) o = it.first + it.n;
+      s->any_owed = true;
+    }
+    if (st != ZIG_OK) {
+      s->broken = st;
+      for (int& x : b->status) x = st;
+      b->done.store(true);
+      cancel_queued_locked(s, ZIG_EHIP);
+    }
+    s->cv_done.notify_all();
+  } else {
+    std::lock_guard<std::mutex> fl(s->fake_mu);
+    s->fake_q.push_back(b);
+    s->fake_cv.notify_one();
+  }
+  s->inflight[k].push_back(b);
+  s->cv_inflight.notify_all();
+}
+
 void sched_loop(Server* s) {
   if (s->device) (void)hipSetDevice(s->dev_id);
   std::unique_lock<std::mutex> lk(s->mu);
   const uint64_t window = (uint64_t)s->cfg.window_us * 1000;
   for (;;) {
     int k = 0, j = 0;
-    s->cv_sched.wait(lk, [&] {
+    auto ready = [&] {
       return s->stop.load() || (!s->intake.empty() && !s->replaying_naive && s->broken == ZIG_OK &&
                                 free_slot(s, &k, &j) && s->arena.fits(s->intake.front().bytes));
-    });
+    };
+    while (!ready()) {
+      // spin a little before parking, so that a request arriving now is
+      // taken up in about a microsecond rather than after a thread wake-up
+      const uint64_t seen = s->work_epoch.load(std::memory_order_acquire);
+      lk.unlock();
+      const uint64_t until = now_ns() + kSchedSpinNs;
+      bool moved = false;
+      do {
+        std::this_thread::yield();
+        moved = s->work_epoch.load(std::memory_order_acquire) != seen || s->stop.load();
+      } while (!moved && now_ns() < until);
+      lk.lock();
+      if (!moved) s->cv_sched.wait(lk, ready);
+    }
     if (s->stop.load()) break;
     if (window) {  // gathering window after the oldest queued submission
       const uint64_t deadline = s->tickets[s->intake.front().ticket].comp.t_submit_ns + window;
@@ -358,105 +548,12 @@ void sched_loop(Server* s) {
       if (s->stop.load()) break;
       if (s->intake.empty() || !free_slot(s, &k, &j)) continue;
     }
-    Batch* b = new Batch();
-    b->id = s->next_batch++;
-    b->stream = k;
-    b->slot = j;
-    const uint64_t t_admit = now_ns();
-    bool rejected = false;
-    while (!s->intake.empty() && b->items.size() < s->cfg.max_batch) {
-      Pending& p = s->intake.front();
-      uint64_t off;
-      if (!s->arena.alloc(p.bytes, &off)) break;  // FIFO: later requests wait too
-      Ticket& tk = s->tickets[p.ticket];
-      uint64_t& next = s->next_host[p.client];
-      int st = ZIG_OK;
-      if (p.spec.n > UINT64_MAX - next)  // indices up to 2^64 - 2, so a counter never wraps
-        st = ZIG_EINVAL;
-      else if (!s->device && s->cfg.fake_fail_every && ++s->fake_seen % s->cfg.fake_fail_every == 0)
-        st = ZIG_EHIP;
-      if (st != ZIG_OK) {  // completes now, uses no index
-        s->arena.release(off, p.bytes);
-        tk.comp.t_admit_ns = tk.comp.t_launch_ns = t_admit;
-        s->stats.failed_requests += 1;
-        s->queued_bytes -= Arena::round(p.bytes);
-        const uint64_t id = p.ticket;
-        s->intake.pop_front();
-        complete_locked(s, id, st, t_admit);
-        rejected = true;
-        continue;
-      }
-      tk.off = off;
-      tk.bytes = p.bytes;
-      tk.state = kLaunched;
-      tk.comp.t_admit_ns = t_admit;
-      tk.comp.out = arena_base(s) + off;
-      tk.comp.batch_id = b->id;
-      tk.comp.first_index = next;
-      Item item;
-      item.client = p.client;
-      item.dist = p.spec.dist;
-      item.dtype = p.spec.dtype;
-      item.n = p.spec.n;
-      item.first = next;
-      item.scale = p.scale;
-      item.shift = p.shift;
-      item.out = tk.comp.out;
-      item.copy_to = tk.copy_to;
-      next += p.spec.n;
-      b->items.push_back(item);
-      b->tickets.push_back(p.ticket);
-      s->queued_bytes -= Arena::round(p.bytes);
-      s->intake.pop_front();
-    }
-    if (rejected) s->cv_done.notify_all();
-    if (b->items.empty()) {
-      delete b;
-      continue;
-    }
-    b->status.assign(b->items.size(), ZIG_OK);
-    s->slots[k][j].busy = true;
-    s->next_stream = (k + 1) % (int)s->cfg.streams;
-    const uint64_t t_launch = now_ns();
-    for (uint64_t tid : b->tickets) {
-      Ticket& tk = s->tickets[tid];
-      tk.comp.batch_size = (uint32_t)b->items.size();
-      tk.comp.t_launch_ns = t_launch;
-    }
-    s->stats.batches += 1;
-    s->stats.requests += b->items.size();
-    for (const Item& it : b->items) s->stats.samples += it.n;
-    if (s->arena.used() > s->stats.max_bytes_in_use) s->stats.max_bytes_in_use = s->arena.used();
-    s->inflight_count += 1;
-    if (s->inflight_count > s->stats.max_inflight_batches) s->stats.max_inflight_batches = s->inflight_count;
-    if (s->device) {
-      // The slot is ours and the indices are fixed: launch without the lock,
-      // so submitters and completions are not held up by the HIP calls.
-      s->launching += 1;
-      lk.unlock();
-      const int st = launch_device(s, b);
-      lk.lock();
-      s->launching -= 1;
-      b->launch_status = st;
-      if (st != ZIG_OK) {
-        s->broken = st;
-        for (int& x : b->status) x = st;
-        b->done.store(true);
-        cancel_queued_locked(s, ZIG_EHIP);
-      }
-      s->cv_done.notify_all();
-    } else {
-      std::lock_guard<std::mutex> fl(s->fake_mu);
-      s->fake_q.push_back(b);
-      s->fake_cv.notify_one();
-    }
-    s->inflight[k].push_back(b);
-    s->cv_inflight.notify_all();
+    form_and_launch(s, lk, k, j);
   }
 }
 
-void finish_locked(Server* s, Batch* b) {
-  const uint64_t t = now_ns();
+// t: when the batch's completion was observed.
+void finish_locked(Server* s, Batch* b, uint64_t t) {
   for (size_t i = 0; i < b->tickets.size(); ++i) {
     if (b->status[i] != ZIG_OK) s->stats.failed_requests += 1;
     complete_locked(s, b->tickets[i], b->status[i], t);
@@ -490,17 +587,19 @@ void complete_loop(Server* s, int k) {
       }
       std::this_thread::yield();
     }
+    const uint64_t t_seen = now_ns();
     lk.lock();
     if (failed) {
       for (int& x : b->status) x = ZIG_EHIP;
       s->broken = ZIG_EHIP;
     }
-    finish_locked(s, b);
+    finish_locked(s, b, t_seen);
     q.pop_front();
     s->inflight_count -= 1;
     delete b;
     s->cv_done.notify_all();
-    s->cv_sched.notify_all();
+    // a slot is free: only queued work needs the scheduler woken
+    if (!s->intake.empty() || s->stop.load()) zig::wake_sched(s);
   }
 }
 
@@ -517,6 +616,7 @@ void free_device(Server* s) {
     if (st) (void)hipStreamDestroy(st);
   s->fill_streams.clear();
   if (s->counters_dev) (void)hipFree(s->counters_dev);
+  if (s->raise_dev) (void)hipFree(s->raise_dev);
   if (s->own_arena && s->arena_dev) (void)hipFree(s->arena_dev);
 }
 
@@ -543,6 +643,7 @@ int setup_device(Server* s) {
   }
   ZIG_CK(hipMalloc(&s->counters_dev, s->cfg.clients * sizeof(uint64_t)), "hipMalloc(counters)");
   ZIG_CK(hipMemset(s->counters_dev, 0, s->cfg.clients * sizeof(uint64_t)), "hipMemset(counters)");
+  ZIG_CK(hipMalloc(&s->raise_dev, s->cfg.clients * sizeof(uint64_t)), "hipMalloc(counter raises)");
   s->fill_streams.assign(s->cfg.streams, nullptr);
   const size_t bbytes = sizeof(BatchHeader) + (size_t)kServeMaxBatch * sizeof(BatchReq);
   for (uint32_t k = 0; k < s->cfg.streams; ++k) {
@@ -612,7 +713,7 @@ int submit_impl(Server* s, uint32_t client, const zig_spec& spec, uint32_t flags
   p.bytes = bytes;
   s->intake.push_back(p);
   s->queued_bytes += Arena::round(bytes);
-  s->cv_sched.notify_all();
+  zig::wake_sched(s);
   return ZIG_OK;
 }
 
@@ -651,6 +752,7 @@ int zig_server_create(const zig_server_cfg* cfg, zig_server** out) {
   s->device = c.backend == ZIG_BACKEND_DEVICE;
   s->arena.init(c.cap_bytes);
   s->next_host.assign(c.clients, 0);
+  s->owed.assign(c.clients, 0);
   s->slots.assign(c.streams, std::vector<zig::DevSlot>(2));
   s->inflight.assign(c.streams, std::deque<zig::Batch*>());
   if (s->device) {
@@ -713,7 +815,7 @@ int zig_server_release(zig_server* srv, uint64_t ticket) {
   if (it->second.state != zig::kDone) return zig::fail(ZIG_ESTATE, "request not complete");
   if (it->second.bytes) s->arena.release(it->second.off, it->second.bytes);
   s->tickets.erase(it);
-  s->cv_sched.notify_all();
+  zig::wake_sched(s);
   return ZIG_OK;
 }
 
@@ -753,7 +855,7 @@ int zig_server_drop_client(zig_server* srv, uint32_t client, uint64_t* reclaimed
   }
   if (reclaimed) *reclaimed = n;
   s->cv_done.notify_all();
-  s->cv_sched.notify_all();
+  zig::wake_sched(s);
   return ZIG_OK;
 }
 
@@ -765,6 +867,8 @@ int zig_server_counters(zig_server* srv, uint64_t* next_index, uint32_t count) {
   std::unique_lock<std::mutex> lk(s->mu);  // no batch can be formed meanwhile
   s->cv_done.wait(lk, [&] { return s->launching == 0; });
   if (s->device) {
+    const int r = zig::pay_owed_locked(s);
+    if (r != ZIG_OK) return r;
     hipError_t e = hipSuccess;
     for (hipStream_t st : s->fill_streams)
       if (e == hipSuccess) e = hipStreamSynchronize(st);  // every launched batch has raised its counters
@@ -790,6 +894,8 @@ int zig_server_set_counters(zig_server* srv, const uint64_t* next_index, uint32_
     if (e != hipSuccess) return zig::fail(ZIG_EHIP, std::string("counter restore: ") + hipGetErrorString(e));
   }
   std::memcpy(s->next_host.data(), next_index, count * sizeof(uint64_t));
+  std::fill(s->owed.begin(), s->owed.end(), 0);  // the restored values replace any owed raise
+  s->any_owed = false;
   return ZIG_OK;
 }
 
@@ -829,7 +935,7 @@ int zig_server_destroy(zig_server* srv) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop.store(true);
     zig::cancel_queued_locked(s, ZIG_ESTATE);
-    s->cv_sched.notify_all();
+    zig::wake_sched(s);
     s->cv_inflight.notify_all();
   }
   s->sched.join();
@@ -956,7 +1062,7 @@ int replay_naive(Server* s, const zig_trace_item* items, uint64_t count, zig_com
       if (d.bytes) {
         std::lock_guard<std::mutex> al(s->mu);
         s->arena.release(d.off, d.bytes);
-        s->cv_sched.notify_all();
+        zig::wake_sched(s);
       }
       lk.lock();
       q[k].pop_front();
@@ -1025,7 +1131,7 @@ int replay_naive(Server* s, const zig_trace_item* items, uint64_t count, zig_com
         if (allocated) {
           std::lock_guard<std::mutex> al(s->mu);
           s->arena.release(off, bytes);
-          s->cv_sched.notify_all();
+          zig::wake_sched(s);
         }
       }
       std::lock_guard<std::mutex> lk(qm);
@@ -1046,7 +1152,7 @@ int replay_naive(Server* s, const zig_trace_item* items, uint64_t count, zig_com
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->replaying_naive = false;
-    s->cv_sched.notify_all();
+    zig::wake_sched(s);
   }
   if (result != ZIG_OK) set_error(message);
   return result;
