@@ -12,6 +12,8 @@ accelerated normal variant, all tile shapes, a range of 2^28 outputs, the
 moments of the fill's own output, determinism, and argument checks."""
 import math
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -155,7 +157,9 @@ def test_moments_per_thread_stream_and_capture(env):
     torch, zig = env
     s = torch.empty(5, dtype=torch.float64, device="cuda")
     zig.zig_moments(NORMAL, F64, 9, 3, 3_000_001, 1.0, 2.0, s.data_ptr(), 2)  # hipStreamPerThread
-    torch.cuda.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+    assert hip.hipStreamSynchronize(ctypes.c_void_p(2)) == 0
     ref = zig.moments(NORMAL, F64, 3_000_001, 9, 3, 1.0, 2.0).cpu().numpy()
     assert s.cpu().numpy().tobytes() == ref.tobytes()
     side = torch.cuda.Stream()
