@@ -18,7 +18,10 @@
  *    default stream of the current device (hipStreamPerThread is accepted
  *    too).  Fills are asynchronous: they return after enqueueing, launch
  *    failures return ZIG_EHIP, and a device fault surfaces at the caller's
- *    next synchronisation.
+ *    next synchronisation.  Work enqueued on hipStreamPerThread is
+ *    synchronised by that thread (for instance with
+ *    hipStreamSynchronize(hipStreamPerThread)) before the thread ends: a
+ *    device-wide synchronisation afterwards need not wait for it.
  *  - Scratch: a fill of more than 16 tiles per compute unit takes its
  *    tiles from an atomic counter pair; the library owns a ring of 64 such
  *    pairs per device (allocated on first use, kept until the process
