@@ -369,6 +369,52 @@ def autotune_report(zig):
     return {"seconds": round(secs, 2), "fill": rows, "batch": c["batch"]}
 
 
+def slow_lane_stats(torch, zig, n=1 << 24):
+    """Slow-lane and queue statistics from the trace build (per-output
+    layer, first region, slow-stream words and density tests) over n
+    outputs of each headline fill: the measured slow share against
+    1 - L/i_max, slow-stream words and density tests per output (for the
+    normal every box decision, squeezed or not), the share of
+    64-block wave slices holding a slow output, and, per tile of the shape
+    the headline size runs (2^30 outputs), the slow outputs a tile hands to
+    its drain (mean, p99, max) and the drain's rounds (the longest
+    slow-stream chain, in Philox blocks, among them)."""
+    res = {}
+    i32 = torch.int32
+    for dist, name, seed, p0, p1 in [(0, "exp", 11, 2.5, 0.0), (1, "normal", 12, -1.0, 3.0)]:
+        for dtype, tname in [(0, "f64"), (1, "f32")]:
+            per_block = 2 if dtype == 0 else 4
+            wg, spl, _ = zig.zig_tuned_shape(dist, dtype, N_C3)
+            tile = wg * spl * per_block
+            out = torch.empty(n, dtype=torch.float64 if dtype == 0 else torch.float32, device="cuda")
+            layer, region, words, tests = (torch.empty(n, dtype=i32, device="cuda") for _ in range(4))
+            zig.zig_fill_trace(dist, dtype, seed, 0, n, p0, p1, out.data_ptr(), layer.data_ptr(),
+                               region.data_ptr(), words.data_ptr(), tests.data_ptr())
+            torch.cuda.synchronize()
+            slow = region >= 0
+            blocks = torch.where(slow, (words + 1) // 2, torch.zeros_like(words))
+            nt = n // tile
+            per_tile = slow[:nt * tile].view(nt, tile).sum(1).double()
+            rounds = blocks[:nt * tile].view(nt, tile).max(1).values.double()
+            wave = slow[:(n // (64 * per_block)) * 64 * per_block].view(-1, 64 * per_block).any(1)
+            res["%s_%s" % (name, tname)] = {
+                "outputs": n,
+                "slow_share": round(float(slow.double().mean()), 6),
+                "slow_share_analytic": round(1 - zig.zig_get_tables(dist, 256)["L"] / 256.0, 6),
+                "slow_words_per_output": round(float(words.double().sum()) / n, 5),
+                "density_tests_per_output": round(float(tests.double().sum()) / n, 6),
+                "wave_slices_with_slow_output": round(float(wave.double().mean()), 4),
+                "tile": "%dx%d (%d outputs)" % (wg, spl, tile),
+                "slow_per_tile": {"mean": round(float(per_tile.mean()), 2),
+                                  "p99": float(torch.quantile(per_tile, 0.99)), "max": float(per_tile.max())},
+                "drain_rounds_per_tile": {"mean": round(float(rounds.mean()), 3), "max": float(rounds.max())},
+                "slow_stream_blocks_per_slow_output": round(float(blocks.double().sum() / slow.sum()), 4),
+            }
+            del out, layer, region, words, tests, slow, blocks
+            torch.cuda.empty_cache()
+    return res
+
+
 def cpu_model():
     """The host CPU's model line from /proc/cpuinfo (empty if unreadable)."""
     try:
@@ -531,6 +577,9 @@ def main():
         log("modified vs traditional ziggurat")
         result["traditional_ab"] = traditional_ab(torch, zig)
         log("traditional_ab: %s" % json.dumps(result["traditional_ab"]))
+        log("slow-lane statistics (trace build)")
+        result["slow_lanes"] = slow_lane_stats(torch, zig)
+        log("slow_lanes: %s" % json.dumps(result["slow_lanes"]))
         log("1024 against 256 layers")
         result["layers_1024"] = layers_ab(torch, zig)
         log("layers_1024: %s" % json.dumps(result["layers_1024"]))
