@@ -1,7 +1,7 @@
 """GPU parity of the wide-table kernels (512 and 1024 layers, Appendix D
 item 1) against the oracle, through the C ABI: per-output traces (layer,
 first region, slow words, density tests), whole fills at several launch
-shapes with a ragged tail, and 2^30 fills in sampled chunks.
+shapes with a ragged tail, and 2^30 fills in sampled chunks and in full.
 
 Bar: as for the 256-layer fills, FP64 outputs bit-identical on the fast
 path and within 4 ulp on the slow paths with identical decisions; FP32
@@ -75,5 +75,31 @@ def test_full_size_sampled(O, env, dist, dtype):
     for s in starts:
         got = out[s:s + size].cpu().numpy()
         parity(got, oracle_fill(O, dist, dtype, seed, s, size, p0, p1, i_max=1024), ULP[dtype])
+    del out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", [F64, F32])
+@pytest.mark.parametrize("dist", [EXP, NORMAL])
+def test_full_size_full_parity(O, env, dist, dtype):
+    """The same 2^30 fills with 1024 layers, every output against the
+    oracle in chunks of 2^26 (no decision may differ)."""
+    torch, zig = env
+    n = 1 << 30
+    seed = 11 if dist == EXP else 12
+    p0, p1 = (2.5, 0.0) if dist == EXP else (-1.0, 3.0)
+    out = gpu_fill(dist, dtype, seed, 0, n, p0, p1, launch={"i_max": 1024})
+    torch.cuda.synchronize()
+    chunk = 1 << 26
+    total_nd, total_mu = 0, 0
+    for s in range(0, n, chunk):
+        got = out[s:s + chunk].cpu().numpy()
+        nd, mu = parity(got, oracle_fill(O, dist, dtype, seed, s, chunk, p0, p1, i_max=1024), ULP[dtype])
+        total_nd += nd
+        total_mu = max(total_mu, mu)
+    print("wide full d%d t%d: %d not bit-identical, max %d ulp" % (dist, dtype, total_nd, total_mu), flush=True)
+    if dtype == F64:
+        assert total_nd == 0
     del out
     torch.cuda.empty_cache()
