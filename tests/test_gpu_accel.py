@@ -2,7 +2,8 @@
 (ZIG_LAUNCH_NORMAL_ACCEL): per-output trace parity with the oracle's
 variant (layer, first region, slow-stream words, density evaluations and
 values), full fills in both output types at several table sizes and
-launch shapes, and the exponential ignoring the flag (the fused moments
+launch shapes, 2^30 fills element by element, and the exponential
+ignoring the flag (the fused moments
 with the variant are covered with the other moments tests)."""
 import numpy as np
 import pytest
@@ -57,6 +58,29 @@ def test_fill_parity(O, env, dtype, i_max, wg, spl):
     zig.fill(plain, NORMAL, 31, 7, -1.0, 3.0, launch={"i_max": i_max})
     same = (to_np(plain).view(it) == got.view(it)).mean()
     assert 0.95 < same < 1.0
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", [F64, F32])
+def test_full_size_full_parity(O, env, dtype):
+    """N(-1, 3), 2^30 outputs with the variant at the default shape (the
+    configuration the benchmark times in FP64), every output against the
+    oracle's variant in chunks of 2^26: bit-identical."""
+    torch, zig = env
+    n = 1 << 30
+    out = torch.empty(n, dtype=torch.float64 if dtype == F64 else torch.float32, device="cuda")
+    zig.fill(out, NORMAL, 12, 0, -1.0, 3.0, launch={"flags": ACCEL})
+    torch.cuda.synchronize()
+    it = np.int64 if dtype == F64 else np.int32
+    chunk = 1 << 26
+    bad = 0
+    for s in range(0, n, chunk):
+        want = O.fill(NORMAL, dtype, 12, s, chunk, 3.0, -1.0, threads=16, accel=True)
+        bad += int(np.count_nonzero(out[s:s + chunk].cpu().numpy().view(it) != want.view(it)))
+    print("accel full t%d: %d outputs differ" % (dtype, bad), flush=True)
+    assert bad == 0
+    del out
+    torch.cuda.empty_cache()
 
 
 def test_exponential_ignores_flag(env):

@@ -106,6 +106,24 @@ def test_full_size_sampled(O, env, dist):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("dist", [EXP, NORMAL])
+def test_full_size_full_parity(O, env, dist):
+    """The same 2^30 FP64 fills, every output against the oracle's
+    traditional sampler in chunks of 2^26."""
+    torch, zig = env
+    n = 1 << 30
+    seed = 11 if dist == EXP else 12
+    p0, p1 = (1.0, 0.0) if dist == EXP else (0.0, 1.0)
+    out = _gpu(env, dist, seed, 0, n, p0, p1)
+    torch.cuda.synchronize()
+    chunk = 1 << 26
+    for s in range(0, n, chunk):
+        _same(out[s:s + chunk].cpu().numpy(), _oracle(O, dist, seed, s, chunk, p0, p1))
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_rejects_fp32_and_accel(env):
     torch, zig = env
     out = torch.empty(16, dtype=torch.float32, device="cuda")
