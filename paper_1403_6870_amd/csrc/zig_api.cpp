@@ -13,6 +13,7 @@
 
 #include "../../include/zig.h"
 #include "zig_internal.hpp"
+#include "zig_ring.hpp"
 #include "zig_tune.hpp"
 
 namespace zig {
@@ -188,24 +189,16 @@ int device_trad(uint32_t i_max, const DevTrad** out) {
   return ZIG_OK;
 }
 
-// Per-launch device scratch of the persistent kernels, handed out from a
-// ring of slots per device: a large fill's tile-counter pair, the moments
-// kernel's partial sums.  Each launch takes the next slot; the stream it
-// runs on first waits for the event recorded after the slot's previous
-// launch, so no two launches ever share a slot at the same time, whatever
-// streams or host threads they come from.  (The fill kernel's last
-// workgroup leaves its counters at zero for the slot's next user.)  The
-// ring's lock is held from taking a slot until its event is recorded.
-struct SlotRing {
-  std::mutex mu;
-  char* base = nullptr;
-  size_t slot_bytes = 0;
-  uint32_t slots = 0, next = 0;
-  std::vector<hipEvent_t> ev;
-  std::vector<char> recorded;
+// HIP's streams and events for the scratch-slot rings (zig_ring.hpp).
+struct HipRingOps {
+  using Event = hipEvent_t;
+  using Stream = void*;
+  static int wait(void* s, hipEvent_t e) { return (int)hipStreamWaitEvent(static_cast<hipStream_t>(s), e, 0); }
+  static int record(hipEvent_t e, void* s) { return (int)hipEventRecord(e, static_cast<hipStream_t>(s)); }
 };
+using HipSlotRing = SlotRing<HipRingOps>;
 
-int ring_init(SlotRing* r, uint32_t slots, size_t slot_bytes) {
+int ring_init(HipSlotRing* r, uint32_t slots, size_t slot_bytes) {
   hipError_t e = hipMalloc(&r->base, slots * slot_bytes);
   if (e != hipSuccess) {
     r->base = nullptr;
@@ -224,32 +217,12 @@ int ring_init(SlotRing* r, uint32_t slots, size_t slot_bytes) {
   return ZIG_OK;
 }
 
-// Runs launch(slot) on `stream` with the next slot of r.  launch returns 0
-// or a hipError_t value, which is passed on.
-template <class F>
-int ring_launch(SlotRing* r, void* stream, F launch) {
-  std::lock_guard<std::mutex> lk(r->mu);
-  const uint32_t k = r->next;
-  r->next = (r->next + 1) % r->slots;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (r->recorded[k]) {
-    const hipError_t e = hipStreamWaitEvent(st, r->ev[k], 0);
-    if (e != hipSuccess) return (int)e;
-  }
-  const int e = launch(static_cast<void*>(r->base + k * r->slot_bytes));
-  if (e != 0) return e;
-  const hipError_t er = hipEventRecord(r->ev[k], st);
-  if (er != hipSuccess) return (int)er;
-  r->recorded[k] = 1;
-  return 0;
-}
-
 constexpr uint32_t kCounterSlots = 64;
 constexpr uint32_t kMomentSlots = 4;
 
 struct DeviceScratch {
-  SlotRing counters;  // 2 x uint32 per slot
-  SlotRing moments;   // kMomMaxGroups x 5 doubles per slot
+  HipSlotRing counters;  // 2 x uint32 per slot
+  HipSlotRing moments;   // kMomMaxGroups x 5 doubles per slot
   int cus = 0;
 };
 std::mutex g_cmu;

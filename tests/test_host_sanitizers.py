@@ -1,7 +1,8 @@
 """Host code under sanitizers (CPU only): the serving scheduler, driven on
-its host fake backend by a multi-threaded stress program, under
-ThreadSanitizer and under AddressSanitizer + UndefinedBehaviorSanitizer;
-the oracle's entry points under AddressSanitizer + UBSan.  Each program is
+its host fake backend by a multi-threaded stress program, and the
+per-launch scratch-slot ring on a simulated device, under ThreadSanitizer
+and under AddressSanitizer + UndefinedBehaviorSanitizer; the oracle's
+entry points under AddressSanitizer + UBSan.  Each program is
 built with g++/gcc from the committed sources (the library's device
 objects are linked as built, uninstrumented) and must print "ok" with no
 sanitizer report."""
@@ -47,6 +48,27 @@ def test_scheduler_under_sanitizer(tmp_path, san):
     exe = str(tmp_path / "stress")
     _run(["g++", "-fsanitize=" + san, "-o", exe] + objs + DEVICE_OBJS +
          ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lquadmath", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    out = _run([exe], env=env, timeout=600)
+    assert out.strip().endswith("ok"), out[-4000:]
+    assert "WARNING: ThreadSanitizer" not in out and "ERROR: AddressSanitizer" not in out
+    assert "runtime error" not in out
+
+
+@pytest.mark.parametrize("san", ["thread", "address,undefined"])
+def test_slot_ring_under_sanitizer(tmp_path, san):
+    """The per-launch scratch-slot ring (csrc/zig_ring.hpp) on a simulated
+    device with in-order streams and events: 8 host threads, two of them
+    sharing one stream, launch 24 000 kernels over 3 slots; no kernel may
+    find its slot held by another launch or its counters non-zero.  (With
+    the ring's wait removed the same program reports hundreds of
+    violations.)"""
+    if shutil.which("g++") is None:
+        pytest.skip("needs g++")
+    exe = str(tmp_path / "ring")
+    _run(["g++", "-O1", "-g", "-fsanitize=" + san, "-fno-omit-frame-pointer", "-std=gnu++17",
+          os.path.join(ROOT, "tests", "csrc", "ring_stress.cpp"), "-o", exe, "-lpthread"])
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     out = _run([exe], env=env, timeout=600)
