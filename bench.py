@@ -468,6 +468,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (a kernel of known traffic, for scaling the "
                          "HBM byte counters of a profiler run)")
+    ap.add_argument("--only", choices=["batch", "moments", "slow_lanes"],
+                    help="run only this part and print it as the JSON line (for profiling one kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler shards by index range with no exchange step, "
@@ -483,6 +485,10 @@ def main():
     props = torch.cuda.get_device_properties(0)
     log("device %s, %d CUs" % (props.name, props.multi_processor_count))
     zig.zig_build_tables(256)
+    if args.only:
+        part = {"batch": batch_bench, "moments": moments_bench, "slow_lanes": slow_lane_stats}[args.only]
+        print(json.dumps({"only": args.only, args.only: part(torch, zig)}), flush=True)
+        return
 
     out_e = torch.empty(N_C3, dtype=torch.float64, device=dev)
     out_n = torch.empty(N_C3, dtype=torch.float64, device=dev)

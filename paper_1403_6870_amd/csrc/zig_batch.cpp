@@ -113,21 +113,23 @@ int describe(const zig_request& r, BatchReq* d, uint32_t index) {
 
 void make_descriptor(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double scale,
                      double shift, void* out, BatchReq* d) {
-  const uint64_t per = dtype == ZIG_F64 ? 2 : 4;
+  // outputs per Philox block: 2 (FP64) or 4 (FP32), as a shift and a mask
+  const uint32_t sh = dtype == ZIG_F64 ? 1 : 2;
+  const uint64_t mask = (1ull << sh) - 1;
   const uint64_t esize = dtype == ZIG_F64 ? 8 : 4;
   std::memset(d, 0, sizeof(*d));
   d->seed = seed;
   d->first = first;
   d->last = first + (n - 1);
-  d->blk0 = d->first / per;
-  d->blk_last = d->last / per;
-  d->full_lo = d->first / per + (d->first % per != 0);
-  if (d->last % per == per - 1) {
-    d->full_hi = d->last / per;
+  d->blk0 = d->first >> sh;
+  d->blk_last = d->last >> sh;
+  d->full_lo = (d->first >> sh) + ((d->first & mask) != 0);
+  if ((d->last & mask) == mask) {
+    d->full_hi = d->last >> sh;
     d->has_full = d->full_lo <= d->full_hi;
   } else {
-    d->full_hi = d->last / per == 0 ? 0 : d->last / per - 1;
-    d->has_full = d->last / per > 0 && d->full_lo <= d->full_hi;
+    d->full_hi = (d->last >> sh) == 0 ? 0 : (d->last >> sh) - 1;
+    d->has_full = (d->last >> sh) > 0 && d->full_lo <= d->full_hi;
   }
   d->out = out;
   d->scale = scale;
@@ -167,38 +169,20 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   if (!batch_shape_supported(wg, spl)) return fail(ZIG_EINVAL, "unsupported batch workgroup size / blocks per lane");
   if (flags & ~ZIG_BATCH_NO_GRAPH) return fail(ZIG_EINVAL, "unknown batch flags");
   const uint64_t tile_blocks = (uint64_t)wg * spl;
+  // tiles of a request: a shift when the tile is a power of two blocks
+  uint32_t tile_shift = 0;
+  while ((1ull << tile_shift) < tile_blocks) ++tile_shift;
+  const bool pow2 = (1ull << tile_shift) == tile_blocks;
 
-  // descriptors into a temporary host array first (validation before any
-  // device work)
-  std::vector<BatchReq> desc;
-  desc.reserve(count);
-  uint64_t total = 0;
-  for (uint32_t i = 0; i < count; ++i) {
-    BatchReq d;
-    int r = describe(reqs[i], &d, i);
-    if (r != ZIG_OK) return r;
-    if (reqs[i].n == 0) continue;
-    const uint64_t blocks = d.blk_last - d.blk0 + 1;
-    const uint64_t t = blocks / tile_blocks + (blocks % tile_blocks != 0);
-    if (total + t >= (1ull << 31)) return fail(ZIG_EINVAL, "batch too large (more than 2^31 tiles)");
-    d.tiles = (uint32_t)t;
-    d.tile_start = (uint32_t)total;
-    total += t;
-    desc.push_back(d);
-  }
-  if (desc.empty()) return ZIG_OK;
-
+  // Validation and descriptors in one pass, written straight into the slot's
+  // pinned buffer (or, for a few requests, the kernel-argument block); a
+  // request that fails validation leaves the slot unlaunched and unused.
   const DevTable* tabs = nullptr;
   int r = device_tables_for(256, &tabs);
   if (r != ZIG_OK) return r;
   uint32_t groups = 0;
   hipError_t e = (hipError_t)batch_groups(wg, spl, false, &groups);
   if (e != hipSuccess) return hip_fail("batch occupancy", e);
-  const bool full = batch_full(total, groups);
-  if (full) {
-    e = (hipError_t)batch_groups(wg, spl, true, &groups);
-    if (e != hipSuccess) return hip_fail("batch occupancy", e);
-  }
 
   int dev = 0;
   e = hipGetDevice(&dev);
@@ -212,28 +196,45 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   }
   std::lock_guard<std::mutex> lk(db->mu);
   Slot& s = db->slots[db->next];
-  db->next = (db->next + 1) % kSlots;
   if (s.used) {
     e = hipEventSynchronize(s.done);
     if (e != hipSuccess) return hip_fail("hipEventSynchronize(batch slot)", e);
   }
-  const uint32_t m = (uint32_t)desc.size();
-  r = ensure_capacity(s, m);
+  r = ensure_capacity(s, count);
   if (r != ZIG_OK) return r;
-
-  const uint32_t chunk = batch_chunk(total, tile_blocks, groups);
-  const uint32_t grid = groups;
-
-  // a batch of a few requests passes its descriptors in the kernel
-  // arguments and is launched directly: no copy, no graph
-  const bool inline_desc = m <= kInlineReqs;
+  const bool inline_desc = count <= kInlineReqs;
   BatchInline inl;
   BatchHeader* h = inline_desc ? &inl.hdr : static_cast<BatchHeader*>(s.host);
-  std::memset(h, 0, sizeof(*h));
+  BatchReq* q = reinterpret_cast<BatchReq*>(h + 1);
+  uint32_t m = 0;
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    r = describe(reqs[i], &q[m], i);
+    if (r != ZIG_OK) return r;
+    if (reqs[i].n == 0) continue;
+    BatchReq& d = q[m];
+    const uint64_t blocks = d.blk_last - d.blk0 + 1;
+    const uint64_t t = pow2 ? (blocks + tile_blocks - 1) >> tile_shift : (blocks + tile_blocks - 1) / tile_blocks;
+    if (total + t >= (1ull << 31)) return fail(ZIG_EINVAL, "batch too large (more than 2^31 tiles)");
+    d.tiles = (uint32_t)t;
+    d.tile_start = (uint32_t)total;
+    total += t;
+    ++m;
+  }
+  if (m == 0) return ZIG_OK;
+  db->next = (db->next + 1) % kSlots;
+
+  const bool full = batch_full(total, groups);
+  if (full) {
+    e = (hipError_t)batch_groups(wg, spl, true, &groups);
+    if (e != hipSuccess) return hip_fail("batch occupancy", e);
+  }
+  const uint32_t chunk = batch_chunk(total, tile_blocks, groups);
+  const uint32_t grid = groups;
   h->count = m;
   h->total_tiles = (uint32_t)total;
   h->chunk = chunk;
-  std::memcpy(h + 1, desc.data(), (size_t)m * sizeof(BatchReq));
+  h->pad = 0;
 
   BatchArgs ba;
   ba.hdr = static_cast<const BatchHeader*>(s.dev);
