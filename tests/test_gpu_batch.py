@@ -168,3 +168,24 @@ def test_batch_unknown_flag_rejected(env):
     with pytest.raises(zig.ZigError) as e:
         zig.zig_fill_batch(arr, torch.cuda.current_stream().cuda_stream, {"flags": 4})
     assert e.value.status == zig.ZIG_EINVAL
+
+
+def test_rejected_batch_leaves_slots_usable(env):
+    """Descriptors are written into the slot as the requests are checked:
+    a large batch rejected at request 20 launches nothing, and the batches
+    after it (more than the four slots, on and off the graph path) match
+    the single fills bit for bit."""
+    torch, zig = env
+    reqs = mixed_requests(np.random.default_rng(9), 40, 14)
+    outs = _alloc(torch, reqs)
+    arr = (zig.Request * (len(reqs) + 1))()
+    for k, ((dist, dt, seed, first, n, p0, p1), o) in enumerate(zip(reqs, outs)):
+        arr[k if k < 20 else k + 1] = zig.Request(dist, dt, seed, first, n, p0, p1, o.data_ptr() if n else None)
+    arr[20] = zig.Request(1, 0, 99, 0, 10, 0.0, -1.0, outs[0].data_ptr())  # sigma < 0
+    with pytest.raises(zig.ZigError) as e:
+        zig.zig_fill_batch(arr, torch.cuda.current_stream().cuda_stream)
+    assert e.value.status == zig.ZIG_EINVAL and "request 20" in str(e.value)
+    want = _single(torch, zig, reqs)
+    for k in range(6):
+        opts = {"flags": zig.BATCH_NO_GRAPH} if k % 2 else None
+        assert _same(_batch(torch, zig, reqs, opts), want), k
