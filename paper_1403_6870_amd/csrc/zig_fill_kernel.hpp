@@ -64,8 +64,13 @@ struct FillShape {
 // smaller footprint fits one more workgroup on a CU (lean_shape).
 // The traditional sampler (TRAD) keeps its quick-accept thresholds and
 // layer heights in T and f and has no use for X and A.
+// A tile with at most kListCap slow outputs lists their staging places
+// (LIST kernels), so that each drain lane finds its output with one LDS
+// read instead of a search of the prefix sums.
+constexpr uint32_t kListCap = 128;
+
 template <uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers, bool SLOWLDS = (CAP <= kLdsLayers),
-          bool TRAD = false>
+          bool TRAD = false, bool LIST = false>
 struct FillLds {
   using Sh = FillShape<DT, WG, S>;
   static constexpr uint32_t SLOW_XA = SLOWLDS && !TRAD ? CAP : 1;
@@ -78,6 +83,7 @@ struct FillLds {
   typename Sh::VecT stage[Sh::TILE];
   uint64_t slowmap[Sh::NWORD];
   uint32_t prefix[Sh::NWORD + 1];
+  uint16_t list[LIST ? kListCap : 1];
   uint32_t tile;
 };
 
@@ -114,10 +120,12 @@ struct TileLds {
   void* stage;
   uint64_t* slowmap;
   uint32_t* prefix;
+  uint16_t* list;  // LIST kernels only
 };
 
-template <uint32_t DIST, uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers, bool SLOWLDS = (CAP <= kLdsLayers)>
-__device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG, S, CAP, SLOWLDS>& sh) {
+template <uint32_t DIST, uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers, bool SLOWLDS = (CAP <= kLdsLayers),
+          bool LIST = false>
+__device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG, S, CAP, SLOWLDS, false, LIST>& sh) {
   const DevTable* tb = a.tab;
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < CAP; i += WG) {
@@ -188,8 +196,12 @@ __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a,
 // WIDE marks tables of more than 256 layers: a 32-bit word then gives
 // s = b > 8 low bits to the index, so its magnitude starts at bit s (the
 // normal's sign sits at bit s); otherwise s = 8.
+//
+// With LIST set, wave 0 also writes the staging places of a tile's slow
+// outputs, in entry order, to sh.list when there are at most kListCap of
+// them.
 template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
-          bool WIDE = false>
+          bool WIDE = false, bool LIST = false>
 __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t) {
   using Sh = FillShape<DT, WG, S>;
   using OutT = typename Sh::OutT;
@@ -341,25 +353,50 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
       run += cnt[k];
     }
     if (lane == 63) sh.prefix[NWORD] = incl;
+    if constexpr (LIST) {
+      // each lane lists the set bits of its words, from its prefix on
+      if (__shfl(incl, 63) <= kListCap) {
+        uint32_t pos = incl - mine;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int w = lane * PER + k;
+          uint64_t bits = (w < NWORD) ? sh.slowmap[w] : 0ull;
+          const uint32_t so = (uint32_t)w / NWAVE, wv = (uint32_t)w % NWAVE;
+          const uint32_t base = ((so / O) * WG + wv * 64) * O + so % O;
+          while (bits) {
+            const uint32_t ln = (uint32_t)__ffsll((unsigned long long)bits) - 1;
+            bits &= bits - 1;
+            sh.list[pos++] = (uint16_t)(base + ln * O);
+          }
+        }
+      }
+    }
   }
   __syncthreads();
   const uint32_t total = sh.prefix[NWORD];
   for (uint32_t e = tid; e < total; e += WG) {
-    // the word holding entry e: prefix[lo] <= e < prefix[lo + 1]
-    uint32_t lo = 0, hi = NWORD;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (sh.prefix[mid] <= e)
-        lo = mid;
-      else
-        hi = mid;
+    uint32_t blk, o;
+    if (LIST && total <= kListCap) {
+      const uint32_t pl = sh.list[e];
+      blk = pl / O;
+      o = pl % O;
+    } else {
+      // the word holding entry e: prefix[lo] <= e < prefix[lo + 1]
+      uint32_t lo = 0, hi = NWORD;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sh.prefix[mid] <= e)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      uint64_t bits = sh.slowmap[lo];
+      for (uint32_t r = e - sh.prefix[lo]; r > 0; --r) bits &= bits - 1;
+      const uint32_t ln = (uint32_t)__ffsll((unsigned long long)bits) - 1;
+      const uint32_t so = lo / NWAVE, wv = lo % NWAVE;
+      o = so % O;
+      blk = (so / O) * WG + wv * 64 + ln;
     }
-    uint64_t bits = sh.slowmap[lo];
-    for (uint32_t r = e - sh.prefix[lo]; r > 0; --r) bits &= bits - 1;
-    const uint32_t ln = (uint32_t)__ffsll((unsigned long long)bits) - 1;
-    const uint32_t so = lo / NWAVE, wv = lo % NWAVE;
-    const uint32_t s = so / O, o = so % O;
-    const uint32_t blk = s * WG + wv * 64 + ln;
     const uint64_t g = (tile0 + blk) * O + o;
     OutT* place = stage_s + blk * O + o;
     bool neg = false;
@@ -451,17 +488,21 @@ fill_kernel(FillArgs a) {
   static_assert(!(WIDE && (TRAD || ACCEL)), "wide tables: the plain modified sampler");
   constexpr uint32_t CAP = WIDE ? kMaxLayers : kLdsLayers;
   constexpr bool SLOWLDS = !WIDE && !lean_shape(WG, S);
-  __shared__ FillLds<DT, WG, S, CAP, SLOWLDS, TRAD> sh;
+  // the slow-output list pays for the exponential (2^30 FP64: 1.57 ->
+  // 1.53 ms); in the normal kernel its registers cost more than it saves
+  constexpr bool LIST = DIST == kDistExp && !TRAD && !WIDE;
+  __shared__ FillLds<DT, WG, S, CAP, SLOWLDS, TRAD, LIST> sh;
   const FillCtx c = [&] {
     if constexpr (TRAD)
       return load_trad_tables<DIST, WG, S, SLOWLDS>(a, sh);
     else
-      return load_tables<DIST, DT, WG, S, CAP, SLOWLDS>(a, sh);
+      return load_tables<DIST, DT, WG, S, CAP, SLOWLDS, LIST>(a, sh);
   }();
   TileLds tl;
   tl.stage = sh.stage;
   tl.slowmap = sh.slowmap;
   tl.prefix = sh.prefix;
+  tl.list = sh.list;
   // Tile schedule: with counters, chunks of a.chunk tiles taken from
   // counters[0]; without, workgroup w takes tiles w, w + G, ...
   const bool dynamic = a.counters != nullptr;
@@ -481,7 +522,7 @@ fill_kernel(FillArgs a) {
     }
     if (t0 >= a.tiles) break;
     for (uint64_t t = t0; t < t1; ++t) {
-      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE>(a, c, tl, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE, LIST>(a, c, tl, (uint32_t)t);
       __syncthreads();
     }
   }
