@@ -67,8 +67,9 @@ void to_device_layout(const HostTable& h, DevTable* d) {
   for (uint32_t i = 0; i < h.i_max; ++i) {
     d->XS[i] = h.XS[i];
     d->XS32[i] = h.XS32[i];
-    d->T[i] = h.T[i];
-    d->A[i] = h.A[i];
+    const uint64_t cap = 1ull << (64 - h.b);
+    const uint64_t t = h.T[i] < cap ? h.T[i] : cap - 1;
+    d->TA[i] = (t << h.b) | h.A[i];
   }
   for (uint32_t j = 0; j <= h.L; ++j) {
     d->X[j] = h.X[j];

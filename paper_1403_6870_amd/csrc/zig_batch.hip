@@ -38,8 +38,7 @@ struct BatchLds {
   float xs32[2][kLdsLayers];
   double X[2][SL + 1];
   double f[2][SL + 1];
-  uint64_t T[2][SL];
-  uint32_t A[2][SL];
+  uint64_t TA[2][SL];
   double2 stage[WG * S];
   uint64_t slowmap[S * 4 * (WG / 64)];  // enough for 4 outputs per block
   uint32_t prefix[S * 4 * (WG / 64) + 1];
@@ -76,8 +75,7 @@ __device__ __forceinline__ void batch_body(const BatchArgs& ba, const BatchHeade
     }
     if constexpr (FULL) {
       for (uint32_t i = tid; i < kLdsLayers; i += WG) {
-        sh.T[d][i] = tb->T[i];
-        sh.A[d][i] = tb->A[i];
+        sh.TA[d][i] = tb->TA[i];
       }
       for (uint32_t i = tid; i <= kLdsLayers; i += WG) {
         sh.X[d][i] = tb->X[i];
@@ -92,12 +90,10 @@ __device__ __forceinline__ void batch_body(const BatchArgs& ba, const BatchHeade
   if constexpr (FULL) {
     vexp.X = sh.X[0];
     vexp.f = sh.f[0];
-    vexp.T = sh.T[0];
-    vexp.A = sh.A[0];
+    vexp.TA = sh.TA[0];
     vnorm.X = sh.X[1];
     vnorm.f = sh.f[1];
-    vnorm.T = sh.T[1];
-    vnorm.A = sh.A[1];
+    vnorm.TA = sh.TA[1];
   }
   TileLds tl;
   tl.stage = sh.stage;

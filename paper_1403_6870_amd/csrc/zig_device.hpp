@@ -74,8 +74,7 @@ struct SlowStream {
 struct TabView {
   const double* X;
   const double* f;
-  const uint64_t* T;
-  const uint32_t* A;
+  const uint64_t* TA;  // alias columns: threshold above the low b bits, alias in them
   const double* XS;
   uint32_t L, imask, b;
   uint64_t keps;
@@ -89,8 +88,7 @@ __device__ __forceinline__ TabView global_view(const DevTable* t) {
   TabView v;
   v.X = t->X;
   v.f = t->f;
-  v.T = t->T;
-  v.A = t->A;
+  v.TA = t->TA;
   v.XS = t->XS;
   v.L = t->L;
   v.imask = t->i_max - 1;
@@ -106,10 +104,12 @@ __device__ __forceinline__ TabView global_view(const DevTable* t) {
 }
 
 // Region draw: column c from the low b bits, compare the high 64-b bits
-// with the column threshold, else take the column's alias.
+// with the column threshold, else take the column's alias; threshold and
+// alias come in one word.
 __device__ __forceinline__ uint32_t alias_region(const TabView& v, uint64_t r) {
   const uint32_t c = (uint32_t)r & v.imask;
-  return (r >> v.b) < v.T[c] ? c : v.A[c];
+  const uint64_t e = v.TA[c];
+  return (r >> v.b) < (e >> v.b) ? c : (uint32_t)e & v.imask;
 }
 
 __device__ __forceinline__ double lattice53(uint64_t k) { return (double)k * 0x1p-53; }

@@ -78,8 +78,7 @@ struct FillLds {
   typename Sh::OutT xs[CAP];
   double X[SLOW_XA + 1];
   double f[SLOW_FT + 1];
-  uint64_t T[SLOW_FT];
-  uint32_t A[SLOW_XA];
+  uint64_t T[SLOW_FT];  // packed alias columns, or the traditional sampler's thresholds
   typename Sh::VecT stage[Sh::TILE];
   uint64_t slowmap[Sh::NWORD];
   uint32_t prefix[Sh::NWORD + 1];
@@ -138,8 +137,7 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
   c.own = dev::global_view(tb);
   if constexpr (SLOWLDS) {
     for (uint32_t i = tid; i < CAP; i += WG) {
-      sh.T[i] = tb->T[i];
-      sh.A[i] = tb->A[i];
+      sh.T[i] = tb->TA[i];
     }
     for (uint32_t i = tid; i <= CAP; i += WG) {
       sh.X[i] = tb->X[i];
@@ -147,8 +145,7 @@ __device__ __forceinline__ FillCtx load_tables(const FillArgs& a, FillLds<DT, WG
     }
     c.own.X = sh.X;
     c.own.f = sh.f;
-    c.own.T = sh.T;
-    c.own.A = sh.A;
+    c.own.TA = sh.T;
   }
   if constexpr (DT == kF64) c.own.XS = sh.xs;
   c.fast = sh.xs;

@@ -31,8 +31,10 @@ struct DevTable {
   double f[kMaxLayers + 1];
   double W[kMaxLayers + 1];
   double H[kMaxLayers + 1];
-  uint64_t T[kMaxLayers];
-  uint32_t A[kMaxLayers];
+  // alias column c: its threshold in the high 64 - b bits (a full
+  // column's, 2^(64-b), stored one less: it decides nothing, since such a
+  // column is its own alias) and its alias in the low b bits
+  uint64_t TA[kMaxLayers];
   // normal: per-box squeeze of the plain box test on k1 + k2 (the two
   //53-bit uniforms): below SQlo[j] the point is under the density, at or
   // above SQhi[j] it is over it, both with a margin far beyond rounding
@@ -41,7 +43,7 @@ struct DevTable {
 };
 
 // g++ builds the host side and hipcc the device side: both must agree
-static_assert(sizeof(DevTable) == 57432 + 2 * 8 * (kMaxLayers + 1), "DevTable layout");
+static_assert(sizeof(DevTable) == 53336 + 2 * 8 * (kMaxLayers + 1), "DevTable layout");
 
 // Host copy with the same content plus the quantities only tests need.
 struct HostTable {

@@ -57,8 +57,7 @@ struct MomLds {
   typename Sh::OutT xs[kLdsLayers];  // fast-path table, 0 for i >= L
   double X[kLdsLayers + 1];
   double f[kLdsLayers + 1];
-  uint64_t T[kLdsLayers];
-  uint32_t A[kLdsLayers];
+  uint64_t TA[kLdsLayers];
   uint64_t slowmap[2][Sh::NWORD];
   uint32_t prefix[2][Sh::NWORD + 1];
   double red[5][Sh::NWAVE];
@@ -101,8 +100,7 @@ moments_kernel(FillArgs a, uint64_t tiles, double* partial) {
       sh.xs[i] = i < L ? tb->XS[i] : 0.0;
     else
       sh.xs[i] = i < L ? tb->XS32[i] : 0.0f;
-    sh.T[i] = tb->T[i];
-    sh.A[i] = tb->A[i];
+    sh.TA[i] = tb->TA[i];
   }
   for (uint32_t i = tid; i <= kLdsLayers; i += WG) {
     sh.X[i] = tb->X[i];
@@ -111,8 +109,7 @@ moments_kernel(FillArgs a, uint64_t tiles, double* partial) {
   dev::TabView own = dev::global_view(tb);
   own.X = sh.X;
   own.f = sh.f;
-  own.T = sh.T;
-  own.A = sh.A;
+  own.TA = sh.TA;
   const dev::TabView ex = dev::global_view(a.etab);
   const uint32_t imask = own.imask;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
