@@ -480,7 +480,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (a kernel of known traffic, for scaling the "
                          "HBM byte counters of a profiler run)")
-    ap.add_argument("--only", choices=["batch", "moments", "slow_lanes", "c2"],
+    ap.add_argument("--only", choices=["batch", "moments", "slow_lanes", "c2", "serving"],
                     help="run only this part and print it as the JSON line (for profiling one kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -498,8 +498,8 @@ def main():
     log("device %s, %d CUs" % (props.name, props.multi_processor_count))
     zig.zig_build_tables(256)
     if args.only:
-        part = {"batch": batch_bench, "moments": moments_bench, "slow_lanes": slow_lane_stats,
-                "c2": c2_bench}[args.only]
+        part = {"batch": batch_bench, "moments": moments_bench, "slow_lanes": slow_lane_stats, "c2": c2_bench,
+                "serving": lambda t, z: serve_bench(t, z, args.serve_seconds)}[args.only]
         print(json.dumps({"only": args.only, args.only: part(torch, zig)}), flush=True)
         return
 

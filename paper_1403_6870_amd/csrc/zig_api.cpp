@@ -284,7 +284,8 @@ int check_params(uint32_t dist, double p0, double p1, double* scale, double* shi
 
 int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0, double p1,
               void* out, void* stream, const zig_launch* launch, bool trace, uint32_t* t_layer, int32_t* t_region,
-              uint32_t* t_words, uint32_t* t_tests, const Shape* forced, bool force_static = false) {
+              uint32_t* t_words, uint32_t* t_tests, const Shape* forced, bool own = false,
+              uint32_t* own_counters = nullptr) {
   g_error.clear();
   if (dist != kDistExp && dist != kDistNormal) return fail(ZIG_EINVAL, "unknown distribution");
   if (dtype != kF64 && dtype != kF32) return fail(ZIG_EINVAL, "unknown dtype");
@@ -386,7 +387,10 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   bool capturing = false;
   r = stream_capturing(stream, &capturing);
   if (r != ZIG_OK) return r;
-  const bool dynamic = !force_static && !capturing && tiles > (uint64_t)kStaticTilesPerCU * (uint64_t)ds->cus;
+  // a caller with its own counters (own) uses them, or the fixed schedule
+  // when it has none
+  const bool dynamic = (!own || own_counters != nullptr) && !capturing &&
+                       tiles > (uint64_t)kStaticTilesPerCU * (uint64_t)ds->cus;
   const uint64_t chunk = 1ull << 30;  // tiles per launch: the counter stays far from 2^32
   for (uint64_t start = 0; start < tiles; start += chunk) {
     a.blk0 = blk0 + start * tile;
@@ -399,7 +403,7 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
              : wide ? launch_fill_wide(dist, dtype, sh.wg, sh.spl, trace, b, stream)
                     : launch_fill(dist, dtype, sh.wg, sh.spl, trace, b, stream);
     };
-    const int e = dynamic ? ring_launch(&ds->counters, stream, go) : go(nullptr);
+    const int e = !dynamic ? go(nullptr) : own ? go(own_counters) : ring_launch(&ds->counters, stream, go);
     if (e != 0)
       return fail(ZIG_EHIP, std::string("fill launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
   }
@@ -502,10 +506,10 @@ int fill_shaped(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, ui
   return fill_impl(dist, dtype, seed, first, n, p0, p1, out, stream, nullptr, false, nullptr, nullptr, nullptr,
                    nullptr, &shape);
 }
-int fill_static(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0, double p1,
-                void* out, void* stream) {
+int fill_own_counters(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0,
+                      double p1, void* out, void* stream, uint32_t* counters) {
   return fill_impl(dist, dtype, seed, first, n, p0, p1, out, stream, nullptr, false, nullptr, nullptr, nullptr,
-                   nullptr, nullptr, true);
+                   nullptr, nullptr, true, counters);
 }
 void set_error(const std::string& msg) { g_error = msg; }
 void clear_error() { g_error.clear(); }

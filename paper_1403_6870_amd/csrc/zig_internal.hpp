@@ -220,11 +220,13 @@ int batch_groups(uint32_t wg, uint32_t spl, bool full, uint32_t* groups);
 bool batch_full(uint64_t total_tiles, uint32_t lean_groups);
 bool batch_shape_supported(uint32_t wg, uint32_t spl);
 
-// zig_fill with the fixed tile schedule at every size (no counter slot,
-// so no event waits between streams): for callers that keep many fills
-// queued on several streams of their own (zig_api.cpp).
-int fill_static(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0, double p1,
-                void* out, void* stream);
+// zig_fill for callers that keep many fills queued on several streams of
+// their own and own a counter pair per launch in flight (zig_api.cpp): a
+// large fill takes its tiles from `counters` (zero at rest, left at zero)
+// instead of the library's ring, so no event waits couple the streams;
+// with counters null every size uses the fixed tile schedule.
+int fill_own_counters(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint64_t n, double p0,
+                      double p1, void* out, void* stream, uint32_t* counters);
 
 // Shared helpers of the C ABI implementation (zig_api.cpp).
 int device_tables_for(uint32_t i_max, const DevTable** out);

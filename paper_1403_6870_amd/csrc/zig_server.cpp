@@ -269,7 +269,10 @@ int launch_single(Server* s, Batch* b) {
   DevSlot& d = s->slots[b->stream][b->slot];
   const Item& it = b->items[0];
   hipStream_t fs = s->fill_streams[b->stream];
-  int r = fill_static(it.dist, it.dtype, s->cfg.seed_base + it.client, it.first, it.n, it.p0, it.p1, it.out, fs);
+  // the slot's own counter pair: a large request takes the counter
+  // schedule without waiting on another stream
+  int r = fill_own_counters(it.dist, it.dtype, s->cfg.seed_base + it.client, it.first, it.n, it.p0, it.p1, it.out,
+                            fs, d.tile_counters);
   if (r != ZIG_OK) return fail(ZIG_EHIP, std::string("serve: fill: ") + zig_last_error());
   hipError_t e = hipSuccess;
   if (it.copy_to) {
