@@ -30,6 +30,14 @@
  *    every fill enqueued on a stream that is being captured into a graph,
  *    use a fixed tile-to-workgroup schedule with no scratch, so a captured
  *    graph may be replayed on several streams at once.
+ *  - Graph capture: a fill enqueued on a capturing stream allocates and
+ *    copies nothing, so its tables must already be on the device
+ *    (zig_build_tables(i_max), or an earlier uncaptured fill with that
+ *    i_max on that device; for the traditional sampler, an uncaptured
+ *    traditional fill).  Otherwise it returns ZIG_ESTATE and enqueues
+ *    nothing, and the capture stays usable.  zig_moments and the batch
+ *    calls refuse a capturing stream (ZIG_EINVAL); zig_moments_noalloc
+ *    may be captured.
  *  - Determinism: the output at global index k is a pure function of
  *    (distribution, dtype, seed, k, parameters, i_max).  It does not depend
  *    on the stream, launch shape, batch composition or call splitting:
@@ -58,7 +66,7 @@ extern "C" {
 #define ZIG_EHIP 3       /* a HIP runtime call or kernel launch failed */
 #define ZIG_ENOMEM 4     /* device or host allocation failed */
 #define ZIG_EBUSY 5      /* server admission refused (non-blocking submit) */
-#define ZIG_ESTATE 6     /* object in the wrong state (closed server, unknown ticket) */
+#define ZIG_ESTATE 6     /* wrong state (closed server, unknown ticket, tables not built before capture) */
 
 /* distributions and output types */
 #define ZIG_EXP 0u
@@ -163,7 +171,8 @@ int zig_get_trad_tables(uint32_t dist, uint32_t i_max, zig_trad_view* out);
  * Figure 2), then out = fma(RN(1/lambda), x, 0).  dtype ZIG_F64 (double
  * out) or ZIG_F32 (float out).  n = 0 is a no-op.
  * Errors: ZIG_EINVAL (null out with n > 0, bad dtype, lambda not finite
- * or <= 0, first_index + n > 2^64), ZIG_EHIP. */
+ * or <= 0, first_index + n > 2^64), ZIG_ESTATE (capturing stream, tables
+ * not yet on the device), ZIG_EHIP. */
 int zig_fill_exp(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dtype, double lambda, void* out,
                  void* stream);
 
@@ -310,7 +319,9 @@ typedef struct {
  * call returns.  Outputs of different
  * requests must not overlap.  Requests with n = 0 are skipped; an invalid
  * request or an unknown flag fails the whole call with ZIG_EINVAL (a
- * request's index in the message) before any device work. */
+ * request's index in the message) before any device work, and so does a
+ * stream being captured into a graph (the graph would hold one descriptor
+ * slot, which later batches reuse). */
 int zig_fill_batch(const zig_request* reqs, uint32_t count, void* stream);
 int zig_fill_batch_ex(const zig_request* reqs, uint32_t count, void* stream, const zig_batch_opts* opts);
 

@@ -92,8 +92,13 @@ void to_device_layout(const HostTable& h, DevTable* d) {
   }
 }
 
-// device copy for the current device; returns the pair [exp, normal]
-int device_tables(uint32_t i_max, const DevTable** out) {
+constexpr const char* kNotBuilt =
+    "tables of this i_max are not built on this device: call zig_build_tables first";
+
+// device copy for the current device; returns the pair [exp, normal].
+// With build false nothing is built, allocated or copied: tables missing on
+// the device are an error (ZIG_ESTATE).
+int device_tables(uint32_t i_max, const DevTable** out, bool build = true) {
   if (!valid_imax(i_max)) return fail(ZIG_EINVAL, "i_max must be a power of two in [8, 1024]");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -105,6 +110,7 @@ int device_tables(uint32_t i_max, const DevTable** out) {
     *out = it->second;
     return ZIG_OK;
   }
+  if (!build) return fail(ZIG_ESTATE, kNotBuilt);
   HostPair* hp = nullptr;
   int r = host_tables_locked(i_max, &hp);
   if (r != ZIG_OK) return r;
@@ -148,7 +154,7 @@ int host_trad_locked(uint32_t i_max, TradPair** out) {
   return ZIG_OK;
 }
 
-int device_trad(uint32_t i_max, const DevTrad** out) {
+int device_trad(uint32_t i_max, const DevTrad** out, bool build = true) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
@@ -159,6 +165,9 @@ int device_trad(uint32_t i_max, const DevTrad** out) {
     *out = it->second;
     return ZIG_OK;
   }
+  if (!build)
+    return fail(ZIG_ESTATE,
+                "traditional tables of this i_max are not on this device: run one uncaptured traditional fill first");
   TradPair* tp = nullptr;
   int r = host_trad_locked(i_max, &tp);
   if (r != ZIG_OK) return r;
@@ -199,6 +208,15 @@ struct HipRingOps {
 };
 using HipSlotRing = SlotRing<HipRingOps>;
 
+// Releases what a ring holds (a ring whose set-up failed part way).
+void ring_release(HipSlotRing* r) {
+  for (hipEvent_t e : r->ev)
+    if (e) (void)hipEventDestroy(e);
+  r->ev.clear();
+  if (r->base) (void)hipFree(r->base);
+  r->base = nullptr;
+}
+
 int ring_init(HipSlotRing* r, uint32_t slots, size_t slot_bytes) {
   hipError_t e = hipMalloc(&r->base, slots * slot_bytes);
   if (e != hipSuccess) {
@@ -206,11 +224,17 @@ int ring_init(HipSlotRing* r, uint32_t slots, size_t slot_bytes) {
     return fail(ZIG_ENOMEM, std::string("hipMalloc(launch scratch): ") + hipGetErrorString(e));
   }
   e = hipMemset(r->base, 0, slots * slot_bytes);
-  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipMemset(launch scratch): ") + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    ring_release(r);
+    return fail(ZIG_EHIP, std::string("hipMemset(launch scratch): ") + hipGetErrorString(e));
+  }
   r->ev.assign(slots, nullptr);
   for (uint32_t k = 0; k < slots; ++k) {
     e = hipEventCreateWithFlags(&r->ev[k], hipEventDisableTiming);
-    if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+      ring_release(r);
+      return fail(ZIG_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
   }
   r->recorded.assign(slots, 0);
   r->slot_bytes = slot_bytes;
@@ -245,7 +269,10 @@ int device_scratch(DeviceScratch** out) {
   int r = ring_init(&d->counters, kCounterSlots, 2 * sizeof(uint32_t));
   if (r != ZIG_OK) return r;
   r = ring_init(&d->moments, kMomentSlots, (size_t)kMomMaxGroups * 5 * sizeof(double));
-  if (r != ZIG_OK) return r;
+  if (r != ZIG_OK) {
+    ring_release(&d->counters);
+    return r;
+  }
   *out = d.get();
   g_scratch[dev] = std::move(d);
   return ZIG_OK;
@@ -327,12 +354,18 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   }
   if (!shape_supported(sh.wg, sh.spl)) return fail(ZIG_EINVAL, "unsupported workgroup size / samples per lane");
 
+  // A fill enqueued on a stream being captured allocates and copies
+  // nothing (either would break or end the capture): its tables must be on
+  // the device already, and its schedule needs no scratch.
+  bool capturing = false;
+  r = stream_capturing(stream, &capturing);
+  if (r != ZIG_OK) return r;
   const DevTable* tabs = nullptr;
-  r = device_tables(i_max, &tabs);
+  r = device_tables(i_max, &tabs, !capturing);
   if (r != ZIG_OK) return r;
   const DevTrad* ttabs = nullptr;
   if (trad) {
-    r = device_trad(i_max, &ttabs);
+    r = device_trad(i_max, &ttabs, !capturing);
     if (r != ZIG_OK) return r;
   }
 
@@ -382,14 +415,13 @@ int fill_impl(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first, uint
   // statically).  A stream being captured always gets the static schedule,
   // so a graph holds no scratch and may be replayed on any stream.
   DeviceScratch* ds = nullptr;
-  r = device_scratch(&ds);
-  if (r != ZIG_OK) return r;
-  bool capturing = false;
-  r = stream_capturing(stream, &capturing);
-  if (r != ZIG_OK) return r;
+  if (!capturing) {
+    r = device_scratch(&ds);
+    if (r != ZIG_OK) return r;
+  }
   // a caller with its own counters (own) uses them, or the fixed schedule
   // when it has none
-  const bool dynamic = (!own || own_counters != nullptr) && !capturing &&
+  const bool dynamic = !capturing && (!own || own_counters != nullptr) &&
                        tiles > (uint64_t)kStaticTilesPerCU * (uint64_t)ds->cus;
   const uint64_t chunk = 1ull << 30;  // tiles per launch: the counter stays far from 2^32
   for (uint64_t start = 0; start < tiles; start += chunk) {
@@ -446,20 +478,6 @@ int moments_zero(double* sums, void* stream) {
   return ZIG_OK;
 }
 
-// Device tables already built for the current device, without building or
-// allocating anything.
-int existing_device_tables(uint32_t i_max, const DevTable** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return fail(ZIG_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_dev.find(std::make_pair(dev, i_max));
-  if (it == g_dev.end())
-    return fail(ZIG_ESTATE, "tables of this i_max are not built on this device: call zig_build_tables first");
-  *out = it->second;
-  return ZIG_OK;
-}
-
 // Argument block and launch of the moments kernels (shared by the
 // entry points with library-owned and with static scratch).
 int moments_launch(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_index, uint64_t n, double scale,
@@ -498,6 +516,7 @@ int moments_launch(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t first_
 }  // namespace
 
 int device_tables_for(uint32_t i_max, const DevTable** out) { return device_tables(i_max, out); }
+int stream_capturing_for(void* stream, bool* capturing) { return stream_capturing(stream, capturing); }
 int params_for(uint32_t dist, double p0, double p1, double* scale, double* shift) {
   return check_params(dist, p0, p1, scale, shift);
 }
@@ -649,7 +668,7 @@ int zig_moments_noalloc(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t f
   if (r != ZIG_OK) return r;
   if (n == 0) return zig::moments_zero(sums, stream);
   const zig::DevTable* tabs = nullptr;
-  r = zig::existing_device_tables(mc.i_max, &tabs);
+  r = zig::device_tables(mc.i_max, &tabs, false);
   if (r != ZIG_OK) return r;
   double* partial = nullptr;
   const int e = zig::moments_static_scratch(&partial);

@@ -174,11 +174,19 @@ int fill_batch_impl(const zig_request* reqs, uint32_t count, void* stream, const
   while ((1ull << tile_shift) < tile_blocks) ++tile_shift;
   const bool pow2 = (1ull << tile_shift) == tile_blocks;
 
+  // A graph captured from here would hold one descriptor slot and its
+  // counters, which later batches reuse while the graph may replay.
+  bool capturing = false;
+  int r = stream_capturing_for(stream, &capturing);
+  if (r != ZIG_OK) return r;
+  if (capturing)
+    return fail(ZIG_EINVAL, "a batch cannot be captured into a graph: its descriptor slot would be fixed in it");
+
   // Validation and descriptors in one pass, written straight into the slot's
   // pinned buffer (or, for a few requests, the kernel-argument block); a
   // request that fails validation leaves the slot unlaunched and unused.
   const DevTable* tabs = nullptr;
-  int r = device_tables_for(256, &tabs);
+  r = device_tables_for(256, &tabs);
   if (r != ZIG_OK) return r;
   uint32_t groups = 0;
   hipError_t e = (hipError_t)batch_groups(wg, spl, false, &groups);

@@ -230,6 +230,7 @@ int fill_own_counters(uint32_t dist, uint32_t dtype, uint64_t seed, uint64_t fir
 
 // Shared helpers of the C ABI implementation (zig_api.cpp).
 int device_tables_for(uint32_t i_max, const DevTable** out);
+int stream_capturing_for(void* stream, bool* capturing);  // whether stream is being captured into a graph
 int params_for(uint32_t dist, double p0, double p1, double* scale, double* shift);
 void set_error(const std::string& msg);
 void clear_error();

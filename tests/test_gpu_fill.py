@@ -270,6 +270,52 @@ def test_captured_fills_replay_concurrently(torch_cuda):
         assert np.array_equal(b.cpu().numpy().view(np.int64), ref_b.view(np.int64))
 
 
+def test_capture_allocates_nothing(O, torch_cuda):
+    """Under graph capture a fill allocates and copies nothing: with no
+    tables of its i_max on the device (32 layers, used by no other GPU
+    test) it returns ZIG_ESTATE, and a batch is refused on the capturing
+    stream, both without breaking the capture, whose other fill replays
+    bit for bit.  Once zig_build_tables(32) has run, the same fill captures
+    and replays as it runs eagerly."""
+    from paper_1403_6870_amd import zig
+    torch = torch_cuda
+    n = 5003
+    ok = torch.empty(n, dtype=torch.float64, device="cuda")
+    small = torch.empty(n, dtype=torch.float64, device="cuda")
+    ref_ok = to_np(gpu_fill(NORMAL, F64, 4, 7, n, 0.5, 2.0, out=ok)).copy()
+    cap = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=cap):
+        with pytest.raises(zig.ZigError) as e:
+            zig.fill(small, EXP, 4, 0, 1.0, 0.0, launch={"i_max": 32}, stream=cap)
+        assert e.value.status == zig.ZIG_ESTATE and "zig_build_tables" in str(e.value)
+        with pytest.raises(zig.ZigError) as e:
+            zig.fill_batch([(small, EXP, 4, 0, 1.0, 0.0)], stream=cap)
+        assert e.value.status == zig.ZIG_EINVAL and "captured" in str(e.value)
+        zig.fill(ok, NORMAL, 4, 7, 0.5, 2.0, stream=cap)
+    for _ in range(2):
+        ok.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(ok.cpu().numpy().view(np.int64), ref_ok.view(np.int64))
+
+    zig.zig_build_tables(32)
+    ref_small = to_np(gpu_fill(EXP, F64, 4, 0, n, 1.0, 0.0, out=small, launch={"i_max": 32})).copy()
+    parity(ref_small, oracle_fill(O, EXP, F64, 4, 0, n, 1.0, 0.0, i_max=32), ULP[F64])
+    g2 = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g2, stream=cap):
+        zig.fill(small, EXP, 4, 0, 1.0, 0.0, launch={"i_max": 32}, stream=cap)
+    for _ in range(2):
+        small.zero_()
+        torch.cuda.synchronize()
+        g2.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(small.cpu().numpy().view(np.int64), ref_small.view(np.int64))
+
+
 def test_per_thread_streams_from_many_threads(torch_cuda):
     """Large fills (counter-scheduled) on the per-thread stream handle from
     four host threads at once: each launch has its own counter pair, so
