@@ -189,3 +189,53 @@ def test_rejected_batch_leaves_slots_usable(env):
     for k in range(6):
         opts = {"flags": zig.BATCH_NO_GRAPH} if k % 2 else None
         assert _same(_batch(torch, zig, reqs, opts), want), k
+
+
+def c4_requests(count=4096):
+    """The 4096-request mixed batch: per request, in this order from
+    numpy.random.default_rng(4), size floor(2^(20 U)), dist Bernoulli(1/2),
+    then exp lambda ~ U[0.1, 10] or normal mu ~ N(0, 1), sigma ~ U[0.1, 5];
+    FP64, seed = request id, first index 0."""
+    rng = np.random.default_rng(4)
+    out = []
+    for k in range(count):
+        n = int(np.floor(2.0 ** (20.0 * rng.random())))
+        dist = int(rng.random() < 0.5)
+        if dist == EXP:
+            p0, p1 = float(rng.uniform(0.1, 10.0)), 0.0
+        else:
+            p0, p1 = float(rng.normal()), float(rng.uniform(0.1, 5.0))
+        out.append((dist, F64, k, 0, n, p0, p1))
+    return out
+
+
+@pytest.mark.slow
+def test_c4_batch_full_parity(O, env):
+    """The 4096-request batch (3.0e8 FP64 outputs) in one graph launch of
+    the tuned shape: every output of every request against the oracle, no
+    decision may differ."""
+    torch, zig = env
+    reqs = c4_requests()
+    offs, tot = [], 0
+    for r in reqs:
+        offs.append(tot)
+        tot += r[4] + (r[4] & 1)
+    arena = torch.empty(tot, dtype=torch.float64, device="cuda")
+    arr = (zig.Request * len(reqs))()
+    for k, (dist, dt, seed, first, n, p0, p1) in enumerate(reqs):
+        arr[k] = zig.Request(dist, dt, seed, first, n, p0, p1, arena.data_ptr() + 8 * offs[k] if n else None)
+    zig.zig_fill_batch(arr, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    host = arena.cpu().numpy()
+    del arena
+    torch.cuda.empty_cache()
+    total_nd, total_mu, samples = 0, 0, 0
+    for k, (dist, dt, seed, first, n, p0, p1) in enumerate(reqs):
+        if n == 0:
+            continue
+        nd, mu = parity(host[offs[k]:offs[k] + n], oracle_fill(O, dist, dt, seed, first, n, p0, p1), 4)
+        total_nd += nd
+        total_mu = max(total_mu, mu)
+        samples += n
+    print("c4 batch full: %d outputs, %d not bit-identical, max %d ulp" % (samples, total_nd, total_mu), flush=True)
+    assert samples == sum(r[4] for r in reqs) and total_nd == 0
