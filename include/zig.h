@@ -189,8 +189,8 @@ int zig_fill_normal(uint64_t seed, uint64_t first_index, uint64_t n, uint32_t dt
  * "pick": i_max 256; wg/spl from the tuned table.  wg in {64,...,1024}
  * lanes per workgroup and spl in {1,2,4,8} Philox blocks per lane make a
  * tile of wg * spl blocks (at most 2048; also wg 256 with spl 7 or 10,
- * 1792 or 2560 blocks), which is also the depth of the per-workgroup
- * slow-output queue.
+ * 1792 or 2560 blocks), whose slow outputs the workgroup gathers and
+ * finishes together.  The shape never changes the outputs.
  * i_max above 256 (512 or 1024 layers) takes b = log2 i_max index bits:
  * the FP64 word keeps its layout (sign bit 10, magnitude bits 11..63);
  * the FP32 word gives bits 0..b-1 to the index, the exponential's
@@ -372,9 +372,12 @@ int zig_autotune_reset(void);
  * fit into an output arena of cap_bytes (256-byte granules, first fit),
  * gives each its first index from its client's counter in admission order,
  * and launches the admitted requests as one batch on the next free of
- * `streams` fill streams: a copy of the batch descriptors, then the
- * persistent batch kernel of zig_fill_batch, whose last workgroup raises
- * the device counters to the ends of the batch's requests.  A request's
+ * `streams` fill streams.  Several requests go as a copy of the batch
+ * descriptors, then the persistent batch kernel of zig_fill_batch, whose
+ * last workgroup raises the device counters to the ends of the batch's
+ * requests; a lone request goes as the plain fill of that request, and
+ * its client's device counter is raised before the counters are next
+ * read (zig_server_counters, checkpoints).  A request's
  * samples are therefore the zig_fill output of (dist, dtype,
  * seed_base + c, first_index, n, p0, p1) whatever else it was batched
  * with; first_index is reported in its completion.  The output lives in
