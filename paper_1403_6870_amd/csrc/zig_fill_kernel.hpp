@@ -325,7 +325,11 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   __syncthreads();
 
   // B: number the slow outputs (exclusive prefix over the bitmap words, by
-  // wave 0) and share them out over every lane
+  // wave 0) and share them out over every lane.  This is the tile's
+  // critical path, run by one wave while the others wait: it takes issue
+  // priority over the other workgroups' waves on its SIMD until the drain
+  // ends.
+  __builtin_amdgcn_s_setprio(2);
   if (wave == 0) {
     constexpr int PER = (NWORD + 63) / 64;
     uint32_t cnt[PER];
@@ -434,6 +438,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
       if (a.t_tests) a.t_tests[k] = tests;
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
 
   // C: staging tile to HBM.  An interior tile with 16-byte aligned blocks

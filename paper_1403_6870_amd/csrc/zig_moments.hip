@@ -191,7 +191,10 @@ moments_kernel(FillArgs a, uint64_t tiles, double* partial) {
       phase_a(std::false_type());
     __syncthreads();
 
-    // B: number the slow outputs and share them out over every lane
+    // B: number the slow outputs and share them out over every lane; the
+    // prefix pass holds up the workgroup, and the drain the next tile, so
+    // both take issue priority over the other workgroups' phase A
+    __builtin_amdgcn_s_setprio(2);
     if (wave == 0) {
       constexpr int PER = (NWORD + 63) / 64;
       uint32_t cnt[PER];
@@ -255,6 +258,7 @@ moments_kernel(FillArgs a, uint64_t tiles, double* partial) {
       }
       add_powers(acc, v);
     }
+    __builtin_amdgcn_s_setprio(0);
     // no barrier: the next tile writes the other bitmap, and the one after
     // comes behind that tile's two barriers
   }
