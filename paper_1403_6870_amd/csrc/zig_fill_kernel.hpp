@@ -184,7 +184,8 @@ __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a,
 }
 
 // One tile (tile index t of this launch).  Ends with the staging tile
-// written out; callers separate consecutive tiles with a barrier.
+// written out.  A lane's phase C reads only staging places it wrote in
+// phase A, so consecutive tiles need no barrier between them.
 //
 // With TRAD set (FP64 only) the sampler is the traditional ziggurat: the
 // fast word quick-accepts when its magnitude bits lie below the layer's
@@ -523,10 +524,12 @@ fill_kernel(FillArgs a) {
       next += gridDim.x;
     }
     if (t0 >= a.tiles) break;
-    for (uint64_t t = t0; t < t1; ++t) {
+    // No barrier between tiles: in phase C a lane reads only the staging
+    // places it wrote itself in phase A, and the bitmap, prefix sums and
+    // list are last read before the barrier that ends the drain, so the
+    // next tile's phase A overwrites nothing another wave still reads.
+    for (uint64_t t = t0; t < t1; ++t)
       fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE, LIST>(a, c, tl, (uint32_t)t);
-      __syncthreads();
-    }
   }
   // the last workgroup to leave resets the counters for the slot's next user
   if (dynamic && threadIdx.x == 0) {
