@@ -172,7 +172,8 @@ __device__ __forceinline__ void batch_body(const BatchArgs& ba, const BatchHeade
         c.fast = sh.xs32[1];
         fill_tile<kDistNormal, kF32, WG, S, false>(a, c, tl, lt);
       }
-      __syncthreads();
+      // no barrier between tiles (see fill_tile): a lane's stores read only
+      // the staging places it wrote itself, whatever request a tile is of
     }
   }
   if (tid == 0) sh.req = atomicAdd(&ba.counters[1], 1u) == gridDim.x - 1 ? 1u : 0u;
