@@ -417,6 +417,23 @@ __device__ __forceinline__ void store_from_lane0(uint32_t addr, uint64_t v, int 
       : "memory");
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active): a
+// Hillis-Steele scan inside each row of 16 lanes by DPP row shifts of 1, 2,
+// 4 and 8 (lanes shifted in from outside the row read 0), then the totals
+// of the rows below, read from lanes 15, 31 and 47.  No LDS round trips,
+// which a shuffle-based scan pays six times in a row.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 31);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 47);
+  const uint32_t row = (threadIdx.x & 63u) >> 4;
+  return x + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }

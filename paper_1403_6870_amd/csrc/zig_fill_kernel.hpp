@@ -341,12 +341,7 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
       cnt[k] = (w < NWORD) ? (uint32_t)__popcll(sh.slowmap[w]) : 0u;
       mine += cnt[k];
     }
-    uint32_t incl = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t up = __shfl_up(incl, d);
-      if ((int)lane >= d) incl += up;
-    }
+    const uint32_t incl = dev::wave_inclusive_sum(mine);
     uint32_t run = incl - mine;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
