@@ -100,6 +100,7 @@ __device__ __forceinline__ void batch_body(const BatchArgs& ba, const BatchHeade
   tl.slowmap = sh.slowmap;
   tl.prefix = sh.prefix;
   tl.list = nullptr;  // the batch kernel searches the prefix sums
+  tl.marks = nullptr;
 
   const uint32_t count = hdr->count;
   const uint32_t total = hdr->total_tiles;

@@ -434,6 +434,27 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
   return x + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
 }
 
+// Inclusive prefix maximum over the 64 lanes of a wave (all lanes active),
+// built like wave_inclusive_sum; lanes shifted in from outside a row read 0.
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
+  uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  x = x > t ? x : t;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  x = x > t ? x : t;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  x = x > t ? x : t;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  x = x > t ? x : t;
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 31);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 47);
+  const uint32_t row = (threadIdx.x & 63u) >> 4;
+  uint32_t below = row >= 1 ? r0 : 0u;
+  if (row >= 2 && r1 > below) below = r1;
+  if (row >= 3 && r2 > below) below = r2;
+  return x > below ? x : below;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }

@@ -83,6 +83,7 @@ struct FillLds {
   uint64_t slowmap[Sh::NWORD];
   uint32_t prefix[Sh::NWORD + 1];
   uint16_t list[LIST ? kListCap : 1];
+  uint32_t marks[LIST ? 1 : 64];  // kernels without the list: see fill_tile
   uint32_t tile;
 };
 
@@ -119,7 +120,8 @@ struct TileLds {
   void* stage;
   uint64_t* slowmap;
   uint32_t* prefix;
-  uint16_t* list;  // LIST kernels only
+  uint16_t* list;   // LIST kernels only
+  uint32_t* marks;  // MARKS kernels only
 };
 
 template <uint32_t DIST, uint32_t DT, int WG, int S, uint32_t CAP = kLdsLayers, bool SLOWLDS = (CAP <= kLdsLayers),
@@ -197,9 +199,12 @@ __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a,
 //
 // With LIST set, wave 0 also writes the staging places of a tile's slow
 // outputs, in entry order, to sh.list when there are at most kListCap of
-// them.
+// them.  With MARKS set instead, when there are at most 64 (all in wave
+// 0's drain), sh.marks[e] gives entry e's bitmap word and that word's
+// first entry, so a drain lane reads them with one load instead of a
+// binary search over the prefix sums.
 template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
-          bool WIDE = false, bool LIST = false>
+          bool WIDE = false, bool LIST = false, bool MARKS = false>
 __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t) {
   using Sh = FillShape<DT, WG, S>;
   using OutT = typename Sh::OutT;
@@ -350,6 +355,27 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
       run += cnt[k];
     }
     if (lane == 63) sh.prefix[NWORD] = incl;
+    if constexpr (MARKS) {
+      // mark each word's first entry with (word + 1, entry) and carry the
+      // marks to the word's later entries by a prefix maximum
+      // (the lanes of wave 0 exchange the marks through LDS: volatile keeps
+      // the compiler from taking a lane's own earlier store for the value
+      // another lane wrote; LDS accesses of one wave complete in order)
+      if ((uint32_t)__builtin_amdgcn_readlane((int)incl, 63) <= 64u) {
+        typedef __attribute__((address_space(3))) volatile uint32_t LdsWord;
+        LdsWord* const mk = (LdsWord*)sh.marks;
+        mk[lane] = 0u;
+        uint32_t pos = incl - mine;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int w = lane * PER + k;
+          if (w < NWORD && cnt[k] > 0u) mk[pos] = ((uint32_t)(w + 1) << 8) | pos;
+          pos += cnt[k];
+        }
+        const uint32_t here = mk[lane];
+        mk[lane] = dev::wave_inclusive_max(here);
+      }
+    }
     if constexpr (LIST) {
       // each lane lists the set bits of its words, from its prefix on
       if (__shfl(incl, 63) <= kListCap) {
@@ -379,16 +405,24 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
       o = pl % O;
     } else {
       // the word holding entry e: prefix[lo] <= e < prefix[lo + 1]
-      uint32_t lo = 0, hi = NWORD;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (sh.prefix[mid] <= e)
-          lo = mid;
-        else
-          hi = mid;
+      uint32_t lo = 0, first;
+      if (MARKS && total <= 64u) {
+        const uint32_t m = sh.marks[e];
+        lo = (m >> 8) - 1u;
+        first = m & 255u;
+      } else {
+        uint32_t hi = NWORD;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (sh.prefix[mid] <= e)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        first = sh.prefix[lo];
       }
       uint64_t bits = sh.slowmap[lo];
-      for (uint32_t r = e - sh.prefix[lo]; r > 0; --r) bits &= bits - 1;
+      for (uint32_t r = e - first; r > 0; --r) bits &= bits - 1;
       const uint32_t ln = (uint32_t)__ffsll((unsigned long long)bits) - 1;
       const uint32_t so = lo / NWAVE, wv = lo % NWAVE;
       o = so % O;
@@ -501,6 +535,7 @@ fill_kernel(FillArgs a) {
   tl.slowmap = sh.slowmap;
   tl.prefix = sh.prefix;
   tl.list = sh.list;
+  tl.marks = sh.marks;
   // Tile schedule: with counters, chunks of a.chunk tiles taken from
   // counters[0]; without, workgroup w takes tiles w, w + G, ...
   const bool dynamic = a.counters != nullptr;
@@ -524,7 +559,7 @@ fill_kernel(FillArgs a) {
     // list are last read before the barrier that ends the drain, so the
     // next tile's phase A overwrites nothing another wave still reads.
     for (uint64_t t = t0; t < t1; ++t)
-      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE, LIST>(a, c, tl, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE, LIST, !LIST>(a, c, tl, (uint32_t)t);
   }
   // the last workgroup to leave resets the counters for the slot's next user
   if (dynamic && threadIdx.x == 0) {
