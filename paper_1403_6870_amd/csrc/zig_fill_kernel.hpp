@@ -204,7 +204,7 @@ __device__ __forceinline__ FillCtx load_trad_tables(const FillArgs& a,
 // first entry, so a drain lane reads them with one load instead of a
 // binary search over the prefix sums.
 template <uint32_t DIST, uint32_t DT, int WG, int S, bool TRACE, bool ACCEL = false, bool TRAD = false,
-          bool WIDE = false, bool LIST = false, bool MARKS = false>
+          bool WIDE = false, bool LIST = false, bool MARKS = false, bool FRESH = false>
 __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, const TileLds& sh, uint32_t t) {
   using Sh = FillShape<DT, WG, S>;
   using OutT = typename Sh::OutT;
@@ -240,9 +240,18 @@ __device__ __forceinline__ void fill_tile(const FillArgs& a, const FillCtx& c, c
   // A: fast path into the staging tile, slow outputs into the bitmap
   auto phase_a = [&](auto interior_tag) {
     constexpr bool IN = decltype(interior_tag)::value;
+    // FRESH: the slices' block offsets are formed per tile.  Hoisted out
+    // of the persistent loop they hold S register pairs, which left the
+    // normal fill kernels at their register limit with a scratch spill
+    // whose reloads missed L2; the batch kernel, held at 3 waves per SIMD
+    // by its LDS, is faster with them hoisted.
+    uint32_t tid_a = tid;
+    if constexpr (FRESH) asm volatile("" : "+v"(tid_a));
+    (void)tid_a;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const uint64_t m = tile0 + (uint64_t)(s * WG) + tid;
+      const uint64_t m =
+          FRESH ? tile0 + (uint64_t)((uint32_t)(s * WG) + tid_a) : tile0 + (uint64_t)(s * WG) + tid;
       uint32_t c0 = (uint32_t)m, c1 = (uint32_t)(m >> 32), c2 = 0u, c3 = (DT == kF64) ? 0u : 1u;
       dev::philox10(c0, c1, c2, c3, c.k0, c.k1);
       OutT v[O];
@@ -559,7 +568,7 @@ fill_kernel(FillArgs a) {
     // list are last read before the barrier that ends the drain, so the
     // next tile's phase A overwrites nothing another wave still reads.
     for (uint64_t t = t0; t < t1; ++t)
-      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE, LIST, !LIST>(a, c, tl, (uint32_t)t);
+      fill_tile<DIST, DT, WG, S, TRACE, ACCEL, TRAD, WIDE, LIST, !LIST, true>(a, c, tl, (uint32_t)t);
   }
   // the last workgroup to leave resets the counters for the slot's next user
   if (dynamic && threadIdx.x == 0) {
