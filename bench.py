@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # bytes of a 1 GiB device copy to what the same counter read for it; the
 # commands and raw readings are in profiles/fill_kernel_counters.txt.
 # Reset to None whenever the fill kernel changes until it is re-measured.
-TRAFFIC = None
+TRAFFIC = 8595702911
 N_C3 = 1 << 30
 N_C2 = 1 << 28
 
