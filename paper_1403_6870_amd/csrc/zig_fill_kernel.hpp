@@ -531,8 +531,11 @@ fill_kernel(FillArgs a) {
   constexpr bool SLOWLDS = !WIDE && !lean_shape(WG, S);
   // the slow-output list pays for the exponential (2^30 FP64: 1.57 ->
   // 1.53 ms) and, since the slice offsets stopped holding registers
-  // across tiles, for the normal (0.3 % FP64, 0.6 % FP32)
-  constexpr bool LIST = !TRAD && !WIDE;
+  // across tiles, for the normal's large tiles (256 x 7: 0.3 % FP64, 0.6 %
+  // FP32); in its smaller shapes the list's two registers cross a
+  // register granule (6 -> 5 waves per SIMD; 512 x 4 at 2^30 FP64 went
+  // from 1.97 to 2.65 ms), so those keep the entry marks
+  constexpr bool LIST = !TRAD && !WIDE && (DIST == kDistExp || S >= 7);
   __shared__ FillLds<DT, WG, S, CAP, SLOWLDS, TRAD, LIST> sh;
   const FillCtx c = [&] {
     if constexpr (TRAD)
